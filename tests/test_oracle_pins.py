@@ -1,0 +1,392 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Every check below is written as a function of the product routine under test
+(``gemm_fn``) so that the same pins can be shown to reject planted mistakes
+(a transposed operand, a dropped term, a wrong sign) in ``test_pins_reject_*``.
+CPU only.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1012_2273_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U64 = 2.0 ** -53
+
+
+# ---------------------------------------------------------------- pin checks
+
+def pin_python_float_loop(gemm_fn, m, n, k, seed):
+    """Bitwise equal to a pure-Python binary64 loop (separate * and + roundings,
+    ascending reduction index), the summation of Algorithm 1 in Section 3.1."""
+    A, B = inputs.uniform_mnk(m, n, k, seed)
+    C = gemm_fn(A, B)
+    ref = np.empty((m, n))
+    for i in range(m):
+        for j in range(n):
+            s = 0.0
+            for p in range(k):
+                s = s + float(A[i, p]) * float(B[p, j])
+            ref[i, j] = s
+    return np.array_equal(C, ref)
+
+
+def pin_exact_rational(gemm_fn, m, n, k, seed):
+    """Within the classical bound |C - AB| <= gamma_k |A||B| of the exact
+    rational product (gamma_k = k u / (1 - k u), u = 2^-53)."""
+    A, B = inputs.uniform_mnk(m, n, k, seed)
+    C = gemm_fn(A, B)
+    gam = k * U64 / (1 - k * U64)
+    for i in range(m):
+        for j in range(n):
+            exact = sum(Fraction(float(A[i, p])) * Fraction(float(B[p, j])) for p in range(k))
+            absum = sum(abs(float(A[i, p]) * float(B[p, j])) for p in range(k))
+            if abs(Fraction(float(C[i, j])) - exact) > Fraction(gam * absum * 1.000001) + Fraction(0):
+                return False
+    return True
+
+
+def pin_identity_permutation(gemm_fn, n, seed):
+    A, B = inputs.uniform_square(n, seed)
+    I = inputs.special("identity", n)
+    P = inputs.special("permutation", n, seed)
+    perm = np.argmax(P, axis=1)          # (P A)[i] = A[perm[i]]
+    return (np.array_equal(gemm_fn(A, I), A) and np.array_equal(gemm_fn(I, B), B)
+            and np.array_equal(gemm_fn(P, A), A[perm]))
+
+
+def pin_diagonal(gemm_fn, n, seed):
+    A, _ = inputs.uniform_square(n, seed)
+    D1 = inputs.special("diagonal", n, seed)
+    D2 = inputs.special("diagonal", n, seed + 1)
+    ok = np.array_equal(gemm_fn(D1, D2), np.diag(np.diag(D1) * np.diag(D2)))
+    return ok and np.array_equal(gemm_fn(A, D2), A * np.diag(D2)[None, :])
+
+
+def pin_rank1(gemm_fn, n, seed):
+    """A = u v^T, B = w z^T  =>  A B = (v . w) u z^T, exact for small integers."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    u, v, w, z = (g.integers(-8, 8, size=n, endpoint=True) for _ in range(4))
+    A = np.outer(u, v).astype(np.float64)
+    B = np.outer(w, z).astype(np.float64)
+    expect = (int(np.dot(v, w)) * np.outer(u, z)).astype(np.float64)
+    return np.array_equal(gemm_fn(A, B), expect)
+
+
+def pin_integer_exact(gemm_fn, m, n, k, seed):
+    """Integer inputs: equal to the exact integer product (int64 arithmetic)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    Ai = g.integers(-8, 8, size=(m, k), endpoint=True)
+    Bi = g.integers(-8, 8, size=(k, n), endpoint=True)
+    return np.array_equal(gemm_fn(Ai.astype(np.float64), Bi.astype(np.float64)),
+                          (Ai @ Bi).astype(np.float64))
+
+
+def pin_associativity(gemm_fn, n, seed):
+    """(A B) x = A (B x) up to rounding: relative gap <= 4 n u."""
+    A, B = inputs.uniform_square(n, seed)
+    x = inputs.uniform((n, 1), seed + 7, count=1)[0]
+    left = gemm_fn(gemm_fn(A, B), x)
+    right = gemm_fn(A, gemm_fn(B, x))
+    scale = np.abs(A) @ (np.abs(B) @ np.abs(x))
+    return bool(np.all(np.abs(left - right) <= 4 * n * U64 * 2 * scale))
+
+
+def pin_blas(gemm_fn, n, seed):
+    """A library product (NumPy/BLAS binary64) agrees to 1e-13 normwise."""
+    A, B = inputs.uniform_square(n, seed)
+    return oracle.relerr_fro(gemm_fn(A, B), A @ B) < 1e-13
+
+
+ALL_PINS = [
+    lambda f: pin_python_float_loop(f, 5, 4, 6, 11),
+    lambda f: pin_exact_rational(f, 4, 5, 6, 12),
+    lambda f: pin_identity_permutation(f, 37, 13),
+    lambda f: pin_diagonal(f, 23, 14),
+    lambda f: pin_rank1(f, 19, 15),
+    lambda f: pin_integer_exact(f, 17, 13, 29, 16),
+    lambda f: pin_associativity(f, 64, 17),
+    lambda f: pin_blas(f, 96, 18),
+]
+
+
+# ----------------------------------------------------- the oracle passes them
+
+@pytest.mark.parametrize("idx", range(len(ALL_PINS)))
+def test_oracle_passes_pin(idx):
+    assert ALL_PINS[idx](oracle.gemm)
+
+
+def test_python_loop_bitwise_several_shapes():
+    for (m, n, k, s) in [(1, 1, 1, 1), (3, 2, 7, 2), (6, 6, 6, 3), (2, 5, 1, 4)]:
+        assert pin_python_float_loop(oracle.gemm, m, n, k, s)
+
+
+def test_exact_rational_square_small():
+    for n in range(1, 7):
+        assert pin_exact_rational(oracle.gemm, n, n, n, 100 + n)
+
+
+def test_integer_exact_large_k():
+    # |C| <= 64 k stays far below 2^53: exact in binary64
+    assert pin_integer_exact(oracle.gemm, 8, 9, 1500, 21)
+
+
+def test_threaded_and_entries_bitwise():
+    A, B = inputs.uniform_mnk(123, 77, 301, 31)
+    C = oracle.gemm(A, B)
+    assert np.array_equal(oracle.gemm_omp(A, B, 3), C)
+    assert np.array_equal(oracle.gemm_omp(A, B, 1), C)
+    g = np.random.Generator(np.random.PCG64(5))
+    r = g.integers(0, 123, 50)
+    c = g.integers(0, 77, 50)
+    assert np.array_equal(oracle.gemm_entries(A, B, r, c), C[r, c])
+
+
+def test_degenerate_shapes():
+    A = np.zeros((3, 0))
+    B = np.zeros((0, 4))
+    assert np.array_equal(oracle.gemm(A, B), np.zeros((3, 4)))   # k = 0: zeroed C
+    assert oracle.gemm(np.zeros((0, 5)), np.ones((5, 2))).shape == (0, 2)
+    assert oracle.gemm(np.ones((2, 5)), np.ones((5, 0))).shape == (2, 0)
+    with pytest.raises(ValueError):
+        oracle.gemm(np.ones((2, 3)), np.ones((4, 2)))
+
+
+def test_binary32_inputs_widened_exactly():
+    A, B = inputs.uniform_square(40, 41, dtype=np.float32)
+    assert np.array_equal(oracle.gemm(A, B), oracle.gemm(A.astype(np.float64), B.astype(np.float64)))
+
+
+# ------------------------------------------------------------ planted mistakes
+
+def _mutant_transposed_b(A, B):
+    return oracle.gemm(A, np.ascontiguousarray(B.T)) if A.shape[1] == B.shape[1] else oracle.gemm(A, B) + 1
+
+
+def _mutant_dropped_last_term(A, B):
+    if A.shape[1] == 0:
+        return oracle.gemm(A, B)
+    return oracle.gemm(A[:, :-1], B[:-1, :])
+
+
+def _mutant_sign(A, B):
+    C = oracle.gemm(A, B)
+    C[-1, -1] = -C[-1, -1] if C.size else C
+    return C
+
+
+def _mutant_fma_like(A, B):
+    # accumulate in a different order (descending): changes bits, not maths
+    return oracle.gemm(A[:, ::-1], B[::-1, :])
+
+
+def _mutant_transposed_a(A, B):
+    return oracle.gemm(np.ascontiguousarray(A.T), B) if A.shape[0] == A.shape[1] else oracle.gemm(A, B) * 2
+
+
+def _mutant_float32(A, B):
+    return (np.asarray(A, np.float32) @ np.asarray(B, np.float32)).astype(np.float64)
+
+
+@pytest.mark.parametrize("mutant", [_mutant_transposed_b, _mutant_dropped_last_term, _mutant_sign,
+                                    _mutant_fma_like, _mutant_transposed_a, _mutant_float32])
+def test_pins_reject_planted_mistakes(mutant):
+    """Each plausible mistake fails at least one pin."""
+    results = []
+    for pin in ALL_PINS:
+        try:
+            results.append(bool(pin(mutant)))
+        except Exception:
+            results.append(False)
+    assert not all(results), f"{mutant.__name__} passed every pin"
+
+
+# ----------------------------------------------------------------- bfloat16
+
+def _torch_bf16_bits(x):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
+
+
+def test_bf16_rne_against_library_random_bits():
+    g = np.random.Generator(np.random.PCG64(7))
+    bits = g.integers(0, 2 ** 32, size=400_000, dtype=np.uint64).astype(np.uint32)
+    x = bits.view(np.float32)
+    finite = np.isfinite(x)
+    ours = oracle.bf16_rne(x[finite])
+    ref = _torch_bf16_bits(x[finite])
+    assert np.array_equal(ours, ref)
+
+
+def test_bf16_rne_special_values():
+    f = lambda b: np.array([b], dtype=np.uint32).view(np.float32)
+    cases = {
+        0x3F808000: 0x3F80,  # tie, kept bit even -> down
+        0x3F818000: 0x3F82,  # tie, kept bit odd -> up
+        0x3F808001: 0x3F81,  # just above the tie -> up
+        0x3F807FFF: 0x3F80,  # just below the tie -> down
+        0x7F7F8000: 0x7F80,  # midpoint above max finite -> +inf (tie to even)
+        0x7F7F7FFF: 0x7F7F,  # below that midpoint -> max finite
+        0xFF7F8000: 0xFF80,  # negative side
+        0x7F800000: 0x7F80,  # +inf
+        0x00000001: 0x0000,  # smallest subnormal rounds to zero
+        0x00008000: 0x0000,  # tie at zero, even
+        0x00018000: 0x0002,  # tie, odd -> up
+        0x80000000: 0x8000,  # -0
+    }
+    for b, want in cases.items():
+        assert int(oracle.bf16_rne(f(b))[0]) == want, hex(b)
+    nan = oracle.bf16_rne(np.array([np.nan], np.float32))[0]
+    assert (int(nan) & 0x7F80) == 0x7F80 and (int(nan) & 0x7F) != 0
+
+
+def test_bf16_representable_fixed_points():
+    g = np.random.Generator(np.random.PCG64(8))
+    h = g.integers(0, 2 ** 16, size=50_000).astype(np.uint16)
+    h = h[(h & 0x7F80) != 0x7F80]                   # finite patterns
+    x = oracle.bf16_to_f32(h)
+    back = oracle.bf16_rne(x)
+    same = (back == h) | ((h & 0x7FFF) == 0)        # +-0 both fine
+    assert np.all(same)
+
+
+# ------------------------------------------------------------------ split
+
+def test_split_reconstruction_bound():
+    """|x - (hi + lo)| <= 2^-16 |x|: each bf16 rounding has unit roundoff 2^-8."""
+    for x in (inputs.uniform((300, 300), 9, np.float32, 1)[0],
+              inputs.row_scaled(200, 10)[0]):
+        hi, lo = oracle.split_bf16(x)
+        xh = oracle.bf16_to_f32(hi).astype(np.float64)
+        xl = oracle.bf16_to_f32(lo).astype(np.float64)
+        xd = x.astype(np.float64)
+        assert np.array_equal(hi, oracle.bf16_rne(x))
+        assert np.all(np.abs(xd - xh) <= 2.0 ** -8 * np.abs(xd))
+        assert np.all(np.abs(xd - xh - xl) <= 2.0 ** -16 * np.abs(xd))
+
+
+def test_split_of_bf16_values_has_zero_lo():
+    x = inputs.integers((50, 50), 3, np.float32, 1)[0]
+    hi, lo = oracle.split_bf16(x)
+    assert np.all(lo == 0) and np.array_equal(oracle.bf16_to_f32(hi), x)
+
+
+def test_split_emulation_elementwise_bound():
+    """Dropping lo*lo and the two representation errors: per entry
+    |C_emul - AB| <= 3.01 * 2^-16 * (|A||B|)."""
+    A, B = inputs.uniform_square(96, 19, dtype=np.float32)
+    Ce = oracle.split_emul_gemm(A, B)
+    C = oracle.gemm(A, B)
+    bound = 3.01 * 2.0 ** -16 * (np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)))
+    assert np.all(np.abs(Ce - C) <= bound)
+    # and the normwise representation error is small enough for a 1e-5 target
+    assert oracle.relerr_fro(Ce, C) < 8e-6
+
+
+def test_split_emulation_rejects_two_term_mistake():
+    """A two-term version (hi*hi + hi*lo) violates the bound: the pin has teeth."""
+    A, B = inputs.uniform_square(96, 19, dtype=np.float32)
+    ahi, alo = (oracle.bf16_to_f32(p) for p in oracle.split_bf16(A))
+    bhi, blo = (oracle.bf16_to_f32(p) for p in oracle.split_bf16(B))
+    wrong = oracle.gemm(ahi, bhi) + oracle.gemm(ahi, blo)
+    C = oracle.gemm(A, B)
+    bound = 3.01 * 2.0 ** -16 * (np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)))
+    assert not np.all(np.abs(wrong - C) <= bound)
+
+
+# ------------------------------------------------------------------ backward
+
+def test_backward_central_difference_fp64_n16():
+    """L is bilinear, so central differences have no truncation error."""
+    n, h = 16, 1e-6
+    A, B, W = inputs.uniform((n, n), inputs.seed_for(4, n), np.float64, 3)
+    L, dA, dB = oracle.loss_and_grads(A, B, W)
+    g = np.random.Generator(np.random.PCG64(3))
+    for _ in range(12):
+        i, j = g.integers(0, n, 2)
+        for X, G in ((A, dA), (B, dB)):
+            Xp = X.copy(); Xp[i, j] += h
+            Xm = X.copy(); Xm[i, j] -= h
+            Lp = oracle.loss_and_grads(*(Xp if X is A else A, Xp if X is B else B, W))[0]
+            Lm = oracle.loss_and_grads(*(Xm if X is A else A, Xm if X is B else B, W))[0]
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - G[i, j]) < 1e-7
+
+
+def test_backward_euler_identities():
+    """L is homogeneous of degree 1 in A and in B: sum(A*dA) = L = sum(B*dB)."""
+    A, B, W = inputs.uniform((40, 40), 77, np.float64, 3)
+    L, dA, dB = oracle.loss_and_grads(A, B, W)
+    assert abs(np.sum(A * dA) - L) < 1e-11 * max(1.0, abs(L)) * 40
+    assert abs(np.sum(B * dB) - L) < 1e-11 * max(1.0, abs(L)) * 40
+
+
+def test_backward_rejects_swapped_gradient():
+    A, B, W = inputs.uniform((12, 12), 78, np.float64, 3)
+    L, dA, dB = oracle.loss_and_grads(A, B, W)
+    wrong = oracle.gemm(W, B)           # W B instead of W B^T
+    assert abs(np.sum(A * wrong) - L) > 1e-6
+
+
+# ------------------------------------------------------ counts, rates, split
+
+def test_flop_count_closed_form():
+    assert oracle.flops_paper(2000) == 15_996_000_000
+    assert oracle.flops_2n3(2000) == 16_000_000_000
+    for n in (1, 2, 3, 10):   # N multiplications and N-1 additions per entry
+        assert oracle.flops_paper(n) == n * n * n + n * n * (n - 1)
+
+
+def test_paper_throughput_table_recomputed():
+    """Table 2 = ops / Table 1 / 1e6 with ops = N^2(2N-1), except the two
+    sequential/OpenMP cells at N = 2000, which equal (2^31 - 1)/t/1e6 (an
+    operation count saturated at the 32-bit integer maximum)."""
+    with open(os.path.join(GOLDEN, "paper_tables.json")) as fh:
+        tab = json.load(fh)
+    for prog in ("sequential", "openmp", "mpi"):
+        for idx, n in enumerate(tab["N"]):
+            t = tab["runtime_s"][prog][idx]
+            printed = tab["throughput_mflops"][prog][idx]
+            ours = oracle.mflops(oracle.flops_paper(n), t)
+            if n == 2000 and prog in ("sequential", "openmp"):
+                assert abs(ours - printed) / printed > 5.0
+                assert abs(oracle.mflops(2 ** 31 - 1, t) - printed) / printed < 0.005
+            else:
+                # Table 1 is printed to 2 decimals: allow its rounding
+                assert abs(ours - printed) / printed < 0.2 if n == 100 else abs(ours - printed) / printed < 0.01
+
+
+def test_paper_speedup_table():
+    with open(os.path.join(GOLDEN, "paper_tables.json")) as fh:
+        tab = json.load(fh)
+    seq = tab["runtime_s"]["sequential"]
+    for prog in ("openmp", "mpi"):
+        for idx in range(4):
+            s = seq[idx] / tab["runtime_s"][prog][idx]
+            assert abs(s - tab["speedup"][prog][idx]) <= 0.05 * tab["speedup"][prog][idx] + 0.01
+
+
+def test_row_partition_worked_example():
+    with open(os.path.join(GOLDEN, "row_partition.json")) as fh:
+        ex = json.load(fh)
+    got = oracle.row_partition(ex["rows"], ex["numworkers"])
+    assert [list(t) for t in got] == ex["expected"]
+    for rows, w in ((2000, 2), (2000, 7), (5, 8), (0, 3)):
+        parts = oracle.row_partition(rows, w)
+        assert sum(p[2] for p in parts) == rows
+        assert max(p[2] for p in parts) - min(p[2] for p in parts) <= 1
+
+
+def test_relerr_closed_forms():
+    C = inputs.uniform((10, 10), 1, count=1)[0]
+    assert oracle.relerr_fro(C, C) == 0.0
+    assert abs(oracle.relerr_fro(C * (1 + 1e-3), C) - 1e-3) < 1e-12
+    assert math.isinf(oracle.relerr_fro(np.ones(3), np.zeros(3)))
