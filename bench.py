@@ -1,0 +1,283 @@
+"""Benchmark of the dense product C = A*B on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--paths fp64,split,...]
+
+A step is one pass over every compute row of the hot path on resident,
+seeded synthetic inputs:
+  fp64     gemm_plain binary64, N = 2000, U[-1,1]                 (headline)
+  split    gemm_split (split kernels + 3-term bfloat16 product), N = 2000
+  fp32     gemm_plain binary32, N = 2000
+  bf16     gemm_plain bfloat16 inputs, binary32 output, N = 2000
+  backward gemm_backward binary32 (dA and dB), N = 2048, dC = W
+  grouped  512 products, N log-uniform in [10, 2000], binary64, one replay
+           of the captured persistent launch (tuned policy)
+Each path is bracketed by HIP events on torch's current stream (the stream
+the kernels run on); the step loop is bracketed by device synchronisation.
+``value`` is the binary64 rate 2N^3/t at N = 2000; the split rate and every
+other path are reported beside it with their normwise error against the
+binary64 oracle. ``roofline`` describes the binary64 kernel (MFMA bound);
+``cpu_baseline`` times the oracle (the paper's Algorithm 4 loop on all host
+threads) on the same N = 2000 binary64 product.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # TFLOP/s, dense MFMA
+HBM_PEAK = 8000.0                                    # GB/s
+METRIC = "GFLOP/s (2N^3/t) at N=2000 FP64 vs split-BF16, at stated rel. error"
+ALL_PATHS = ["fp64", "split", "fp32", "bf16", "backward", "grouped"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp64_n2000.json")
+KERNEL_SOURCES = ["paper_1012_2273_amd/csrc/gemm_tile.hpp",
+                  "paper_1012_2273_amd/csrc/kernels_plain.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for_current_kernel():
+    """HBM bytes per launch of the binary64 kernel from the committed counter
+    summary, or None if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--paths", default=",".join(ALL_PATHS))
+    ap.add_argument("--n", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has "
+              "no multi-GPU path: the product would shard by row blocks of A and C "
+              "(see the design notes), which is not built here.", file=sys.stderr)
+        sys.exit(2)
+    paths = [p for p in args.paths.split(",") if p]
+    for p in paths:
+        if p not in ALL_PATHS:
+            sys.exit(f"unknown path {p}")
+
+    import torch
+
+    import paper_1012_2273_amd as G
+    from paper_1012_2273_amd import inputs
+
+    if not os.path.exists(G._lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    G.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N = args.n
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    # ---------------------------------------------------------------- inputs
+    host = {}
+    work = {}          # path -> (callable, algorithmic flops per call)
+    A64, B64 = inputs.uniform_square(N, inputs.seed_for(1, N))
+    host["fp64"] = (A64, B64)
+    A64d, B64d = torch.from_numpy(A64).to(dev), torch.from_numpy(B64).to(dev)
+    C64d = torch.empty((N, N), dtype=torch.float64, device=dev)
+    work["fp64"] = (lambda: G.gemm_plain(A64d, B64d, C64d), 2.0 * N ** 3)
+
+    if any(p in paths for p in ("split", "fp32", "bf16")):
+        A32, B32 = inputs.uniform_square(N, inputs.seed_for(2, N), dtype=np.float32)
+        host["f32"] = (A32, B32)
+        A32d, B32d = torch.from_numpy(A32).to(dev), torch.from_numpy(B32).to(dev)
+        Csd = torch.empty((N, N), dtype=torch.float32, device=dev)
+        ws = torch.empty(G.gemm_split_workspace_size(N, N, N), dtype=torch.uint8, device=dev)
+        work["split"] = (lambda: G.gemm_split(A32d, B32d, Csd, ws), 2.0 * N ** 3)
+        C32d = torch.empty((N, N), dtype=torch.float32, device=dev)
+        work["fp32"] = (lambda: G.gemm_plain(A32d, B32d, C32d), 2.0 * N ** 3)
+        A16d, B16d = A32d.to(torch.bfloat16), B32d.to(torch.bfloat16)
+        C16d = torch.empty((N, N), dtype=torch.float32, device=dev)
+        work["bf16"] = (lambda: G.gemm_plain(A16d, B16d, C16d), 2.0 * N ** 3)
+
+    if "backward" in paths:
+        NB = 2048
+        Ab, Bb, Wb = inputs.uniform((NB, NB), inputs.seed_for(4, NB), np.float32, 3)
+        host["backward"] = (Ab, Bb, Wb)
+        Abd, Bbd, Wbd = (torch.from_numpy(x).to(dev) for x in (Ab, Bb, Wb))
+        bw_out = {}
+
+        def run_bw():
+            bw_out["d"] = G.gemm_backward(Abd, Bbd, Wbd)
+        work["backward"] = (run_bw, 2 * 2.0 * NB ** 3)
+
+    plan = None
+    if "grouped" in paths:
+        log("generating 512-problem batch")
+        sizes = inputs.batch_sizes(512, 3_000_000)
+        gA, gB, gprobs = [], [], []
+        for i, n in enumerate(sizes):
+            A, B = inputs.batch_problem(i, int(n), 3_000_000, np.float64)
+            gprobs.append((A, B))
+            gA.append(torch.from_numpy(A).to(dev))
+            gB.append(torch.from_numpy(B).to(dev))
+        host["grouped"] = (sizes, gprobs)
+        import tempfile
+        cache = os.path.join(tempfile.mkdtemp(prefix="gemm_tune_"), "tune_cache.json")
+        t0 = time.time()
+        plan = G.GroupedPlan(gA, gB, autotune=True, tune_cache=cache)
+        log(f"grouped plan (autotune) {time.time() - t0:.2f}s; tiles/policy {plan.info()}")
+        work["grouped"] = (plan.run, float(sum(2 * int(n) ** 3 for n in sizes)))
+
+    order = [p for p in ALL_PATHS if p in paths]
+
+    # ---------------------------------------------------------------- timing
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        for p in order:
+            work[p][0]()
+    torch.cuda.synchronize()
+    evs = {p: [] for p in order}
+    t_wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in order:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            work[p][0]()
+            e1.record(stream)
+            evs[p].append((e0, e1))
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = {p: float(np.mean([a.elapsed_time(b) for a, b in evs[p]])) for p in order}
+    ms_min = {p: float(np.min([a.elapsed_time(b) for a, b in evs[p]])) for p in order}
+
+    # ---------------------------------------------------------- error check
+    import oracle
+    errs = {}
+    if not args.no_check:
+        A, B = host["fp64"]
+        t0 = time.time()
+        ref64 = oracle.gemm_omp(A, B)
+        errs["fp64"] = oracle.relerr_fro(C64d.cpu().numpy(), ref64)
+        log(f"oracle fp64 N={N}: {time.time() - t0:.1f}s")
+        if "f32" in host:
+            A, B = host["f32"]
+            ref32 = oracle.gemm_omp(A, B)
+            if "split" in order:
+                errs["split"] = oracle.relerr_fro(Csd.cpu().double().numpy(), ref32)
+            if "fp32" in order:
+                errs["fp32"] = oracle.relerr_fro(C32d.cpu().double().numpy(), ref32)
+            if "bf16" in order:
+                errs["bf16"] = oracle.relerr_fro(C16d.cpu().double().numpy(), ref32)
+        if "backward" in order:
+            Ab, Bb, Wb = host["backward"]
+            g = np.random.Generator(np.random.PCG64(1))
+            r = g.integers(0, Ab.shape[0], 400)
+            c = g.integers(0, Ab.shape[0], 400)
+            dA, dB = (t.cpu().double().numpy() for t in bw_out["d"])
+            eA = oracle.relerr_sampled(dA[r, c], oracle.gemm_entries(Wb, np.ascontiguousarray(Bb.T), r, c))
+            eB = oracle.relerr_sampled(dB[r, c], oracle.gemm_entries(np.ascontiguousarray(Ab.T), Wb, r, c))
+            errs["backward"] = max(eA, eB)
+        if "grouped" in order:
+            sizes, gprobs = host["grouped"]
+            worst = 0.0
+            g = np.random.Generator(np.random.PCG64(2))
+            for i in range(0, len(sizes), 4):
+                A, B = gprobs[i]
+                n = int(sizes[i])
+                r = g.integers(0, n, 40)
+                c = g.integers(0, n, 40)
+                got = plan.Cs[i].cpu().numpy()[r, c]
+                worst = max(worst, oracle.relerr_sampled(got, oracle.gemm_entries(A, B, r, c)))
+            errs["grouped"] = worst
+
+    # ---------------------------------------------------------- cpu baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        thr = host_threads()
+        A, B = host["fp64"]
+        t0 = time.perf_counter()
+        oracle.gemm_omp(A, B, thr)
+        tc = time.perf_counter() - t0
+        cpu = {"value": round(2.0 * N ** 3 / tc / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
+               "kind": "oracle",
+               "sample": f"the full N={N} binary64 product, oracle loop (row, column, "
+                         f"reduction; no FMA) with rows split statically over {thr} threads "
+                         f"as in the paper's Algorithm 4; {tc:.2f} s"}
+
+    # ---------------------------------------------------------- report
+    paths_out = {}
+    for p in order:
+        flops = work[p][1]
+        d = {"ms": round(ms[p], 5), "ms_min": round(ms_min[p], 5),
+             "gflops": round(flops / (ms[p] * 1e-3) / 1e9, 2)}
+        if p in errs:
+            d["rel_err"] = float(f"{errs[p]:.3e}")
+        paths_out[p] = d
+    if "split" in paths_out:
+        paths_out["split"]["mfma_util_bf16"] = round(
+            6.0 * N ** 3 / (ms["split"] * 1e-3) / 1e12 / PEAK["bf16"], 4)
+    t_fp64 = ms["fp64"] * 1e-3
+    achieved = 2.0 * N ** 3 / t_fp64 / 1e12
+    traffic = traffic_for_current_kernel()
+    line = {
+        "metric": METRIC,
+        "value": round(2.0 * N ** 3 / t_fp64 / 1e9, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded U[-1,1], row-major)",
+        "config": {"workload": f"square dense product N={N}: binary64 (value) and binary32 "
+                               "3-term bfloat16 split, plus the other paths of the step",
+                   "N": N, "paths": order},
+        "split_bf16": {"value": paths_out.get("split", {}).get("gflops"),
+                       "rel_err": paths_out.get("split", {}).get("rel_err"),
+                       "vs_fp64": (round(ms["fp64"] / ms["split"], 2) if "split" in ms else None)},
+        "fp64_rel_err": paths_out["fp64"].get("rel_err"),
+        "paths": paths_out,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    if plan is not None:
+        plan.close()
+
+
+if __name__ == "__main__":
+    main()

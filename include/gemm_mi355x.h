@@ -1,0 +1,214 @@
+/*
+ * gemm_mi355x.h -- C ABI of the MI355X (gfx950) dense matrix product library.
+ *
+ * The operation is the one Hasta and Mutiara (arXiv 1012.2273) benchmark:
+ * the product of an (m x k) matrix A and a (k x n) matrix B of contiguous
+ * row-major elements into an (m x n) matrix C that is zeroed and then
+ * accumulated (Section 3.1, Algorithm 1; Section 3.1.1, Algorithms 2 and 3;
+ * Section 3.1.2, Algorithm 4). C is therefore OVERWRITTEN with A*B: there is
+ * no alpha/beta scaling.
+ *
+ * Conventions shared by every call
+ *   - Matrices are row-major; a leading dimension (lda, ldb, ...) is the
+ *     distance in ELEMENTS between the starts of two consecutive rows.
+ *   - Matrix pointers are DEVICE pointers owned by the caller; the library
+ *     never frees or retains them. `stream` is a hipStream_t (NULL = the
+ *     null stream). Every call is asynchronous on `stream`: no host
+ *     synchronisation except where stated (plan creation, autotuning).
+ *   - Every call validates its arguments first and launches nothing when
+ *     validation fails. Errors reported later by the device surface at the
+ *     caller's next synchronisation of `stream`.
+ *   - Sizes: m == 0 or n == 0 is a no-op returning GEMM_OK; k == 0 writes
+ *     C = 0 (the zero initialisation of Algorithms 3 and 4).
+ *   - C must not overlap A or B (not checked).
+ *   - Any leading dimension >= the row length is accepted; 16-byte vector
+ *     loads are used when the pointer and leading dimension allow it, scalar
+ *     loads otherwise.
+ *   - Calls are re-entrant; the thread-local text of the last error is
+ *     returned by gemm_last_error().
+ */
+#ifndef GEMM_MI355X_H
+#define GEMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum {
+    GEMM_OK = 0,
+    GEMM_EINVAL = 1,        /* negative size, count or unknown option            */
+    GEMM_ENULL = 2,         /* NULL pointer where data is required               */
+    GEMM_ELD = 3,           /* leading dimension smaller than the row length     */
+    GEMM_EWORKSPACE = 4,    /* workspace missing or smaller than required        */
+    GEMM_EUNSUPPORTED = 5,  /* unknown dtype or dtype not offered by this call   */
+    GEMM_EHIP = 6,          /* the HIP runtime reported an error                 */
+    GEMM_ENOMEM = 7,        /* device or host allocation failed (plans only)     */
+    GEMM_ESTATE = 8         /* plan used in a state that does not allow the call */
+};
+
+/* Element types. */
+enum {
+    GEMM_F64 = 0,   /* A, B, C binary64                                          */
+    GEMM_F32 = 1,   /* A, B, C binary32                                          */
+    GEMM_BF16 = 2   /* A, B bfloat16 (16-bit patterns), C binary32; products are
+                       accumulated in binary32                                   */
+};
+
+/*
+ * gemm_plain -- C(m x n) = A(m x k) * B(k x n) in one dtype on the matrix
+ * cores. Section 3.1, Algorithm 1 (the product) with C zeroed as in
+ * Algorithms 3 and 4; the binary64 path is the paper's precision.
+ *   dtype   GEMM_F64 / GEMM_F32 / GEMM_BF16 (see the enum for C's type).
+ *   A, lda  device, m rows of k elements, lda >= k.
+ *   B, ldb  device, k rows of n elements, ldb >= n.
+ *   C, ldc  device, m rows of n elements, ldc >= n; overwritten.
+ * Errors: EINVAL (m, n or k < 0), ENULL, ELD, EUNSUPPORTED (dtype), EHIP.
+ */
+int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k,
+               const void *A, int64_t lda, const void *B, int64_t ldb,
+               void *C, int64_t ldc, void *stream);
+
+/*
+ * gemm_split_workspace_size -- bytes of device workspace gemm_split needs
+ * for this shape (the four bfloat16 operand planes, 256-byte aligned).
+ * Returns 0 for negative sizes.
+ */
+size_t gemm_split_workspace_size(int64_t m, int64_t n, int64_t k);
+
+/*
+ * gemm_split_convert -- the split step alone: each binary32 element x of
+ * the (rows x cols) matrix X becomes hi = bf16(x) and lo = bf16(x - hi),
+ * both rounded to nearest, ties to even; x - hi is exact in binary32.
+ *   transpose = 0: hi[r][c] at hi + r*ldo + c (ldo >= cols)
+ *   transpose = 1: hi[c][r] at hi + c*ldo + r (ldo >= rows), same for lo.
+ * hi and lo are device arrays of 16-bit patterns owned by the caller.
+ * This is the precision extension of the dense product (the paper fixes
+ * binary64 only); see gemm_split for how the planes are used.
+ * Errors: EINVAL, ENULL, ELD, EHIP.
+ */
+int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                       int transpose, uint16_t *hi, uint16_t *lo, int64_t ldo,
+                       void *stream);
+
+/*
+ * gemm_split -- C(m x n) ~= A(m x k) * B(k x n) for binary32 A, B, C through
+ * a two-way bfloat16 split of both operands and three products accumulated
+ * in binary32 on the matrix cores: C = A_lo*B_hi + A_hi*B_lo + A_hi*B_hi
+ * (A_lo*B_lo is dropped; its size is at most 2^-16 of |A||B|). The same
+ * product as gemm_plain (Section 3.1, Algorithm 1), at a precision close to
+ * binary32.
+ *   workspace  device memory of at least gemm_split_workspace_size(m, n, k)
+ *              bytes, owned by the caller, 16-byte aligned; it holds the
+ *              planes between the split launch and the product launch, so it
+ *              must not be shared by overlapping calls.
+ * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
+ */
+int gemm_split(int64_t m, int64_t n, int64_t k,
+               const float *A, int64_t lda, const float *B, int64_t ldb,
+               float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+               void *stream);
+
+/*
+ * gemm_backward -- gradients of a scalar loss through C = A*B, given
+ * dC = dL/dC (m x n):  dA = dC * B^T  (m x k),  dB = A^T * dC  (k x n).
+ * The transposed operands are read in place (no transposed copy is made).
+ * The differentiated product is the one of Section 3.1, Algorithm 1.
+ *   dtype   GEMM_F64 / GEMM_F32 (all six matrices of that type) or GEMM_BF16
+ *           (A, B, dC bfloat16; dA, dB binary32).
+ *   dA or dB may be NULL to skip that gradient (then its ld is ignored).
+ *   lda >= k, ldb >= n, lddc >= n, ldda >= k, lddb >= n.
+ * Errors: EINVAL, ENULL, ELD, EUNSUPPORTED, EHIP.
+ */
+int gemm_backward(int dtype, int64_t m, int64_t n, int64_t k,
+                  const void *A, int64_t lda, const void *B, int64_t ldb,
+                  const void *dC, int64_t lddc, void *dA, int64_t ldda,
+                  void *dB, int64_t lddb, void *stream);
+
+/* One independent product of a group: C = A*B with the conventions above. */
+typedef struct gemm_problem {
+    int64_t m, n, k;
+    const void *A;
+    const void *B;
+    void *C;
+    int64_t lda, ldb, ldc;
+} gemm_problem;
+
+typedef struct gemm_plan gemm_plan;
+
+/* Plan flags. */
+enum {
+    GEMM_PLAN_AUTOTUNE = 1,   /* time candidate tile policies on the device now */
+    GEMM_PLAN_NO_GRAPH = 2    /* launch directly instead of through a hipGraph  */
+};
+
+/*
+ * gemm_grouped_plan_create -- prepare `count` independent products
+ * (Section 3.1, Algorithm 1, applied to each) for one persistent launch.
+ * The row-block work split of Section 3.1.1 (Algorithm 2) is replaced by a
+ * device work queue of output tiles over all problems, largest first.
+ *   dtype      GEMM_F64 or GEMM_F32.
+ *   probs      host array of `count` descriptors, copied into the plan.
+ *   tune_cache path of a JSON file holding tuned tile policies (read, and
+ *              written after tuning); NULL for none.
+ *   flags      GEMM_PLAN_* bits.
+ *   stream     stream used for the upload, tuning and graph capture; the call
+ *              synchronises it before returning.
+ * The plan owns its device descriptor and queue arrays and its hipGraphExec
+ * until gemm_grouped_plan_destroy. Tuning overwrites the C matrices.
+ * Errors: EINVAL (count < 0, bad flags, negative sizes), ENULL, ELD,
+ * EUNSUPPORTED, ENOMEM, EHIP.
+ */
+int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *probs,
+                             int32_t count, const char *tune_cache, int flags,
+                             void *stream);
+
+/* gemm_grouped_run -- one launch of the plan (a hipGraphLaunch of the
+ * captured queue reset + persistent kernel, unless GEMM_PLAN_NO_GRAPH).
+ * `stream` may differ from the creation stream. Errors: ENULL, EHIP. */
+int gemm_grouped_run(gemm_plan *plan, void *stream);
+
+/* gemm_grouped_plan_update -- replace the A, B, C pointers (and nothing else)
+ * of every problem; sizes and leading dimensions must equal the plan's.
+ * Takes effect for the next run without re-capture; synchronous copy.
+ * Errors: ENULL, EINVAL (count or a size differs), EHIP. */
+int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t count);
+
+/* gemm_grouped_plan_destroy -- free the plan (NULL is a no-op). */
+int gemm_grouped_plan_destroy(gemm_plan *plan);
+
+/* gemm_grouped_plan_info -- number of output tiles and the tile policy
+ * chosen per size class (writes up to `cap` config ids into `policy`). */
+int gemm_grouped_plan_info(const gemm_plan *plan, int64_t *tiles, int32_t *policy,
+                           int32_t cap);
+
+/*
+ * gemm_grouped -- uncaptured convenience: plan with the default policy (or
+ * the last policy tuned for this dtype in this process), run once on
+ * `stream`, release the plan after the stream completes (the call
+ * synchronises `stream`). Errors: as plan_create and run.
+ */
+int gemm_grouped(int dtype, const gemm_problem *probs, int32_t count, void *stream);
+
+/* gemm_strerror -- static text for a return code. */
+const char *gemm_strerror(int status);
+
+/* gemm_last_error -- thread-local detail of the last failing call on this
+ * thread ("" if none). The pointer stays valid until the next call. */
+const char *gemm_last_error(void);
+
+/* gemm_tile_config_count / gemm_tile_config_name -- the tile shapes the
+ * kernels are built for, as "BMxBNxBK"; gemm_plain_force_config(id) makes
+ * gemm_plain use tile config `id` for every dtype (-1 restores the
+ * size-based choice); used by the autotuner and by the tests. */
+int gemm_tile_config_count(void);
+const char *gemm_tile_config_name(int id);
+int gemm_plain_force_config(int id);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEMM_MI355X_H */

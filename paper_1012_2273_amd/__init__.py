@@ -1,0 +1,308 @@
+"""MI355X-native dense matrix product C = A*B (Hasta and Mutiara, arXiv 1012.2273).
+
+Thin Python binding over ``libgemm_mi355x.so``: every function marshals torch
+device tensors into the C ABI (``include/gemm_mi355x.h``) and launches on
+torch's current stream. Every arithmetic step runs in the HIP kernels; there
+is no CPU or PyTorch fallback, and a missing library raises.
+
+Names follow the C ABI: ``gemm_plain``, ``gemm_split``, ``gemm_split_convert``,
+``gemm_backward``, ``gemm_grouped`` (plus :class:`GroupedPlan` for the
+captured, replayable form) and :class:`GemmFn`, an autograd function whose
+backward calls ``gemm_backward``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (GEMM_BF16, GEMM_F32, GEMM_F64, GEMM_PLAN_AUTOTUNE, GEMM_PLAN_NO_GRAPH,
+                   GemmArgError, GemmError)
+
+__all__ = [
+    "gemm_plain", "gemm_split", "gemm_split_convert", "gemm_split_workspace_size",
+    "gemm_backward", "gemm_grouped", "GroupedPlan", "GemmFn", "matmul", "load",
+    "GemmError", "GemmArgError", "GEMM_F64", "GEMM_F32", "GEMM_BF16",
+    "tile_configs", "force_tile_config",
+]
+
+
+def load():
+    """Load the HIP library (raises RuntimeError if it has not been built)."""
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return GEMM_F64
+    if t.dtype == torch.float32:
+        return GEMM_F32
+    if t.dtype == torch.bfloat16:
+        return GEMM_BF16
+    raise GemmArgError(_lib.GEMM_EUNSUPPORTED, "dtype", f"unsupported dtype {t.dtype}")
+
+
+def _out_dtype(code):
+    torch = _torch()
+    return torch.float64 if code == GEMM_F64 else torch.float32
+
+
+def _mat(t, name):
+    """(ptr, ld) of a row-major 2-D device tensor (unit column stride)."""
+    if t.dim() != 2:
+        raise GemmArgError(_lib.GEMM_EINVAL, name, "expected a 2-D tensor")
+    if not t.is_cuda:
+        raise GemmArgError(_lib.GEMM_EINVAL, name, "expected a device tensor")
+    if t.numel() == 0:
+        return ctypes.c_void_p(0), int(max(t.shape[1], 1))
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise GemmArgError(_lib.GEMM_ELD, name, "columns must be contiguous (stride 1)")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), int(ld)
+
+
+def _stream(t):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def gemm_plain(A, B, C=None):
+    """C = A @ B on the matrix cores. float64, float32, or bfloat16 inputs
+    (bfloat16 gives a float32 C). Writes into ``C`` if given."""
+    torch = _torch()
+    code = _dtype_code(A)
+    if B.dtype != A.dtype:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain", "A and B dtypes differ")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain", f"shape mismatch {tuple(A.shape)} x {tuple(B.shape)}")
+    if C is None:
+        C = torch.empty((m, n), dtype=_out_dtype(code), device=A.device)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    lib = _lib.load()
+    _lib.check(lib.gemm_plain(code, m, n, k, pa, lda, pb, ldb, pc, ldc, _stream(A)), "gemm_plain")
+    return C
+
+
+def gemm_split_workspace_size(m, n, k) -> int:
+    return int(_lib.load().gemm_split_workspace_size(int(m), int(n), int(k)))
+
+
+def gemm_split(A, B, C=None, workspace=None):
+    """float32 C ~= A @ B via the two-way bfloat16 split of A and B and three
+    bfloat16 products accumulated in float32."""
+    torch = _torch()
+    if A.dtype != torch.float32 or B.dtype != torch.float32:
+        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, "gemm_split", "float32 inputs required")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_split", "shape mismatch")
+    if C is None:
+        C = torch.empty((m, n), dtype=torch.float32, device=A.device)
+    need = gemm_split_workspace_size(m, n, k)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    lib = _lib.load()
+    _lib.check(lib.gemm_split(m, n, k, pa, lda, pb, ldb, pc, ldc,
+                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                              _stream(A)), "gemm_split")
+    return C
+
+
+def gemm_split_convert(X, transpose=False):
+    """(hi, lo) int16 tensors holding the bfloat16 patterns of X's split;
+    shape X.shape, or transposed when ``transpose``."""
+    torch = _torch()
+    if X.dtype != torch.float32:
+        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, "gemm_split_convert", "float32 input required")
+    r, c = X.shape
+    shape = (c, r) if transpose else (r, c)
+    hi = torch.empty(shape, dtype=torch.int16, device=X.device)
+    lo = torch.empty(shape, dtype=torch.int16, device=X.device)
+    px, ldx = _mat(X, "X")
+    ldo = shape[1] if shape[1] > 0 else 1
+    lib = _lib.load()
+    _lib.check(lib.gemm_split_convert(r, c, px, ldx, int(bool(transpose)),
+                                      ctypes.c_void_p(hi.data_ptr() if hi.numel() else 0),
+                                      ctypes.c_void_p(lo.data_ptr() if lo.numel() else 0),
+                                      ldo, _stream(X)), "gemm_split_convert")
+    return hi, lo
+
+
+def gemm_backward(A, B, dC, need_dA=True, need_dB=True):
+    """(dA, dB) = (dC @ B^T, A^T @ dC) with transposed-operand tiles."""
+    torch = _torch()
+    code = _dtype_code(A)
+    m, k = A.shape
+    n = B.shape[1]
+    if B.shape[0] != k or tuple(dC.shape) != (m, n):
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_backward", "shape mismatch")
+    if B.dtype != A.dtype or dC.dtype != A.dtype:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_backward", "dtypes differ")
+    od = _out_dtype(code)
+    dA = torch.empty((m, k), dtype=od, device=A.device) if need_dA else None
+    dB = torch.empty((k, n), dtype=od, device=A.device) if need_dB else None
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pd, lddc = _mat(dC, "dC")
+    pda, ldda = _mat(dA, "dA") if dA is not None else (ctypes.c_void_p(0), 0)
+    pdb, lddb = _mat(dB, "dB") if dB is not None else (ctypes.c_void_p(0), 0)
+    lib = _lib.load()
+    rc = lib.gemm_backward(code, m, n, k, pa, lda, pb, ldb, pd, lddc,
+                           pda if dA is not None else None, ldda,
+                           pdb if dB is not None else None, lddb, _stream(A))
+    _lib.check(rc, "gemm_backward")
+    return dA, dB
+
+
+def _problems(As, Bs, Cs):
+    arr = (_lib.GemmProblem * len(As))()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        pa, lda = _mat(A, "A")
+        pb, ldb = _mat(B, "B")
+        pc, ldc = _mat(C, "C")
+        arr[i] = _lib.GemmProblem(A.shape[0], B.shape[1], A.shape[1], pa, pb, pc, lda, ldb, ldc)
+    return arr
+
+
+class GroupedPlan:
+    """A captured persistent launch of independent products C_i = A_i @ B_i.
+
+    ``autotune=True`` times candidate tile policies on the given data once
+    (overwriting the C_i); ``tune_cache`` is a JSON path for the chosen policy.
+    ``run()`` replays the captured hipGraph on torch's current stream.
+    """
+
+    def __init__(self, As, Bs, Cs=None, autotune=False, tune_cache=None, graph=True):
+        torch = _torch()
+        if not (len(As) == len(Bs)):
+            raise GemmArgError(_lib.GEMM_EINVAL, "GroupedPlan", "list lengths differ")
+        code = _dtype_code(As[0]) if As else GEMM_F64
+        if Cs is None:
+            Cs = [torch.empty((A.shape[0], B.shape[1]), dtype=A.dtype, device=A.device)
+                  for A, B in zip(As, Bs)]
+        for A, B in zip(As, Bs):
+            if A.shape[1] != B.shape[0] or A.dtype != As[0].dtype or B.dtype != As[0].dtype:
+                raise GemmArgError(_lib.GEMM_EINVAL, "GroupedPlan", "shape or dtype mismatch")
+        self.As, self.Bs, self.Cs = list(As), list(Bs), list(Cs)
+        self._arr = _problems(self.As, self.Bs, self.Cs)
+        self.device = As[0].device if As else torch.device("cuda:0")
+        flags = (GEMM_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else GEMM_PLAN_NO_GRAPH)
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        _lib.check(lib.gemm_grouped_plan_create(
+            ctypes.byref(h), code, self._arr, len(self.As),
+            tune_cache.encode() if tune_cache else None, flags, stream), "gemm_grouped_plan_create")
+        self._h = h
+
+    def run(self):
+        torch = _torch()
+        lib = _lib.load()
+        _lib.check(lib.gemm_grouped_run(
+            self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)),
+            "gemm_grouped_run")
+        return self.Cs
+
+    def update(self, As, Bs, Cs):
+        """Point the plan at new tensors of identical shapes (no re-capture)."""
+        torch = _torch()
+        torch.cuda.current_stream(self.device).synchronize()
+        arr = _problems(As, Bs, Cs)
+        _lib.check(_lib.load().gemm_grouped_plan_update(self._h, arr, len(As)),
+                   "gemm_grouped_plan_update")
+        self.As, self.Bs, self.Cs, self._arr = list(As), list(Bs), list(Cs), arr
+
+    def info(self):
+        tiles = ctypes.c_int64()
+        pol = (ctypes.c_int32 * 7)()
+        _lib.check(_lib.load().gemm_grouped_plan_info(self._h, ctypes.byref(tiles), pol, 7),
+                   "gemm_grouped_plan_info")
+        return int(tiles.value), [tile_configs()[c] for c in pol]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().gemm_grouped_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_grouped(As, Bs, Cs=None):
+    """Uncaptured convenience form: one persistent launch, then synchronise."""
+    torch = _torch()
+    if Cs is None:
+        Cs = [torch.empty((A.shape[0], B.shape[1]), dtype=A.dtype, device=A.device)
+              for A, B in zip(As, Bs)]
+    if not As:
+        return Cs
+    code = _dtype_code(As[0])
+    arr = _problems(As, Bs, Cs)
+    _lib.check(_lib.load().gemm_grouped(code, arr, len(As), _stream(As[0])), "gemm_grouped")
+    return Cs
+
+
+def tile_configs():
+    lib = _lib.load()
+    return [lib.gemm_tile_config_name(i).decode() for i in range(lib.gemm_tile_config_count())]
+
+
+def force_tile_config(cfg_id: int):
+    """Use tile config ``cfg_id`` for every single-product launch (-1: automatic)."""
+    _lib.check(_lib.load().gemm_plain_force_config(int(cfg_id)), "gemm_plain_force_config")
+
+
+def _gemm_fn():
+    torch = _torch()
+
+    class GemmFn(torch.autograd.Function):
+        """C = A @ B with the hand-written backward (dA = dC B^T, dB = A^T dC)."""
+
+        @staticmethod
+        def forward(ctx, A, B):
+            ctx.save_for_backward(A, B)
+            return gemm_plain(A.contiguous(), B.contiguous())
+
+        @staticmethod
+        def backward(ctx, dC):
+            A, B = ctx.saved_tensors
+            dC = dC.to(A.dtype).contiguous()
+            dA, dB = gemm_backward(A.contiguous(), B.contiguous(), dC,
+                                   need_dA=ctx.needs_input_grad[0],
+                                   need_dB=ctx.needs_input_grad[1])
+            return dA, dB
+
+    return GemmFn
+
+
+_GemmFn = None
+
+
+def __getattr__(name):
+    global _GemmFn
+    if name == "GemmFn":
+        if _GemmFn is None:
+            _GemmFn = _gemm_fn()
+        return _GemmFn
+    raise AttributeError(name)
+
+
+def matmul(A, B):
+    """Differentiable C = A @ B through :class:`GemmFn`."""
+    return __getattr__("GemmFn").apply(A, B)

@@ -1,0 +1,264 @@
+// gemm_api.hip -- the C ABI: argument validation, tile-shape choice,
+// dispatch, grouped plans (planner, autotuner, hipGraph capture).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "gemm_mi355x.h"
+#include "gemm_tile.hpp"
+#include "internal.h"
+
+namespace g355 {
+
+static thread_local std::string t_err;
+
+int set_error(int code, const std::string &detail) {
+  t_err = detail;
+  return code;
+}
+void clear_error() { t_err.clear(); }
+
+static const CfgInfo kCfgs[CFG_COUNT] = {
+    {128, 128, "128x128"}, {128, 64, "128x64"}, {64, 64, "64x64"}, {32, 32, "32x32"}};
+const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
+
+static std::atomic<int> g_force_cfg{-1};
+
+static int device_cus() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  cache[dev] = cus;
+  return cus;
+}
+
+// Tile shape for one product: minimise (tiles per CU, rounded up) x tile
+// area / relative efficiency of the shape. Larger tiles re-read less of A
+// and B per flop and keep more independent MFMAs in flight; smaller ones
+// fill the 256 CUs when C is small.
+static int choose_cfg(int prec, int64_t m, int64_t n) {
+  const int forced = g_force_cfg.load();
+  if (forced >= 0 && forced < CFG_COUNT) return forced;
+  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6};
+  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35};
+  const double *eff = (prec == PREC_F64) ? eff_f64 : eff_lp;
+  const int64_t cus = device_cus();
+  int best = CFG_128x128;
+  double best_cost = 0;
+  for (int c = 0; c < CFG_COUNT; ++c) {
+    const int64_t tiles = ((m + kCfgs[c].bm - 1) / kCfgs[c].bm) * ((n + kCfgs[c].bn - 1) / kCfgs[c].bn);
+    const int64_t waves = (tiles + cus - 1) / cus;
+    const double cost = (double)waves * kCfgs[c].bm * kCfgs[c].bn / eff[c];
+    if (c == 0 || cost < best_cost) { best = c; best_cost = cost; }
+  }
+  return best;
+}
+
+static size_t esize_of(int dtype) {
+  switch (dtype) {
+    case GEMM_F64: return 8;
+    case GEMM_F32: return 4;
+    case GEMM_BF16: return 2;
+  }
+  return 0;
+}
+
+static bool aligned16(const void *p, int64_t ld, size_t es) {
+  return ((uintptr_t)p % 16 == 0) && (((uint64_t)ld * es) % 16 == 0);
+}
+
+static int hip_fail(hipError_t e, const char *what) {
+  return set_error(GEMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Shared validation for a row-major (rows x cols) operand.
+static int check_mat(const char *name, const void *p, int64_t rows, int64_t cols, int64_t ld) {
+  if (rows > 0 && cols > 0 && p == nullptr)
+    return set_error(GEMM_ENULL, std::string(name) + " is NULL");
+  if (ld < cols || ld < 0)
+    return set_error(GEMM_ELD, std::string("leading dimension of ") + name + " (" +
+                                   std::to_string(ld) + ") < row length " + std::to_string(cols));
+  return GEMM_OK;
+}
+
+static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hipStream_t s) {
+  if (a.M == 0 || a.N == 0) return GEMM_OK;
+  const int cfg = choose_cfg(prec, a.M, a.N);
+  bool vec = aligned16(a.A, a.lda, es_in) && aligned16(a.B, a.ldb, es_in);
+  if (prec == PREC_SPLIT) vec = true;
+  hipError_t e = launch_plain(prec, layout, cfg, vec, a, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GEMM_OK;
+}
+
+}  // namespace g355
+
+using namespace g355;
+
+extern "C" {
+
+const char *gemm_strerror(int status) {
+  switch (status) {
+    case GEMM_OK: return "success";
+    case GEMM_EINVAL: return "invalid argument";
+    case GEMM_ENULL: return "null pointer";
+    case GEMM_ELD: return "leading dimension too small";
+    case GEMM_EWORKSPACE: return "workspace too small";
+    case GEMM_EUNSUPPORTED: return "unsupported dtype";
+    case GEMM_EHIP: return "HIP runtime error";
+    case GEMM_ENOMEM: return "out of memory";
+    case GEMM_ESTATE: return "invalid plan state";
+  }
+  return "unknown status";
+}
+
+const char *gemm_last_error(void) { return t_err.c_str(); }
+
+int gemm_tile_config_count(void) { return CFG_COUNT; }
+
+const char *gemm_tile_config_name(int id) {
+  if (id < 0 || id >= CFG_COUNT) return "";
+  return kCfgs[id].name;
+}
+
+int gemm_plain_force_config(int id) {
+  if (id >= CFG_COUNT || id < -1) return set_error(GEMM_EINVAL, "tile config id out of range");
+  g_force_cfg.store(id);
+  return GEMM_OK;
+}
+
+int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+               const void *B, int64_t ldb, void *C, int64_t ldc, void *stream) {
+  clear_error();
+  if (dtype != GEMM_F64 && dtype != GEMM_F32 && dtype != GEMM_BF16)
+    return set_error(GEMM_EUNSUPPORTED, "dtype " + std::to_string(dtype));
+  if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
+  int rc;
+  if ((rc = check_mat("A", A, m, k, lda)) || (rc = check_mat("B", B, k, n, ldb)) ||
+      (rc = check_mat("C", C, m, n, ldc)))
+    return rc;
+  if (m == 0 || n == 0) return GEMM_OK;
+  GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
+  const int prec = dtype == GEMM_F64 ? PREC_F64 : dtype == GEMM_F32 ? PREC_F32 : PREC_BF16;
+  return run_product(prec, LAYOUT_NN, a, esize_of(dtype), (hipStream_t)stream);
+}
+
+static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Workspace layout: A_hi | A_lo (m x kp) then B_hi | B_lo (n x kp), kp = k
+// rounded up to 8 elements (16 bytes) so every plane row is 16-byte aligned;
+// each plane starts on a 256-byte boundary.
+static void split_layout(int64_t m, int64_t n, int64_t k, int64_t &kp, size_t off[4],
+                         size_t &total) {
+  kp = round_up(k > 0 ? k : 1, 8);
+  const size_t a_bytes = (size_t)round_up(m * kp * 2, 256);
+  const size_t b_bytes = (size_t)round_up(n * kp * 2, 256);
+  off[0] = 0;
+  off[1] = a_bytes;
+  off[2] = 2 * a_bytes;
+  off[3] = 2 * a_bytes + b_bytes;
+  total = 2 * a_bytes + 2 * b_bytes;
+}
+
+size_t gemm_split_workspace_size(int64_t m, int64_t n, int64_t k) {
+  if (m < 0 || n < 0 || k < 0) return 0;
+  int64_t kp;
+  size_t off[4], total;
+  split_layout(m, n, k, kp, off, total);
+  return total;
+}
+
+int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx, int transpose,
+                       uint16_t *hi, uint16_t *lo, int64_t ldo, void *stream) {
+  clear_error();
+  if (rows < 0 || cols < 0) return set_error(GEMM_EINVAL, "negative size");
+  if (transpose != 0 && transpose != 1) return set_error(GEMM_EINVAL, "transpose must be 0 or 1");
+  int rc;
+  if ((rc = check_mat("X", X, rows, cols, ldx))) return rc;
+  if (rows > 0 && cols > 0 && (hi == nullptr || lo == nullptr))
+    return set_error(GEMM_ENULL, "hi/lo plane is NULL");
+  const int64_t out_cols = transpose ? rows : cols;
+  if (ldo < out_cols) return set_error(GEMM_ELD, "ldo smaller than the plane row length");
+  if (rows == 0 || cols == 0) return GEMM_OK;
+  hipError_t e = launch_split(rows, cols, X, ldx, transpose != 0, hi, lo, ldo, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "split launch");
+  return GEMM_OK;
+}
+
+int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+               int64_t ldb, float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+               void *stream) {
+  clear_error();
+  if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
+  int rc;
+  if ((rc = check_mat("A", A, m, k, lda)) || (rc = check_mat("B", B, k, n, ldb)) ||
+      (rc = check_mat("C", C, m, n, ldc)))
+    return rc;
+  if (m == 0 || n == 0) return GEMM_OK;
+  int64_t kp;
+  size_t off[4], total;
+  split_layout(m, n, k, kp, off, total);
+  if (workspace == nullptr || workspace_bytes < total)
+    return set_error(GEMM_EWORKSPACE, "need " + std::to_string(total) + " bytes, got " +
+                                          std::to_string(workspace_bytes));
+  if ((uintptr_t)workspace % 16 != 0)
+    return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  uint16_t *ahi = (uint16_t *)(ws + off[0]), *alo = (uint16_t *)(ws + off[1]);
+  uint16_t *bhi = (uint16_t *)(ws + off[2]), *blo = (uint16_t *)(ws + off[3]);
+  if (k > 0) {
+    hipError_t e = launch_split(m, k, A, lda, false, ahi, alo, kp, s);
+    if (e == hipSuccess) e = launch_split(k, n, B, ldb, true, bhi, blo, kp, s);
+    if (e != hipSuccess) return hip_fail(e, "split launch");
+  }
+  GemmArgs a{m, n, k, ahi, kp, bhi, kp, alo, blo, C, ldc};
+  return run_product(PREC_SPLIT, LAYOUT_NT, a, 2, s);
+}
+
+int gemm_backward(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                  const void *B, int64_t ldb, const void *dC, int64_t lddc, void *dA,
+                  int64_t ldda, void *dB, int64_t lddb, void *stream) {
+  clear_error();
+  if (dtype != GEMM_F64 && dtype != GEMM_F32 && dtype != GEMM_BF16)
+    return set_error(GEMM_EUNSUPPORTED, "dtype " + std::to_string(dtype));
+  if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
+  int rc;
+  if ((rc = check_mat("dC", dC, m, n, lddc))) return rc;
+  if (dA && ((rc = check_mat("B", B, k, n, ldb)) || (rc = check_mat("dA", dA, m, k, ldda))))
+    return rc;
+  if (dB && ((rc = check_mat("A", A, m, k, lda)) || (rc = check_mat("dB", dB, k, n, lddb))))
+    return rc;
+  const int prec = dtype == GEMM_F64 ? PREC_F64 : dtype == GEMM_F32 ? PREC_F32 : PREC_BF16;
+  const size_t es = esize_of(dtype);
+  hipStream_t s = (hipStream_t)stream;
+  if (dA) {  // dA (m x k) = dC (m x n) * B^T, B stored k x n: K-contiguous op(B)
+    GemmArgs a{m, k, n, dC, lddc, B, ldb, nullptr, nullptr, dA, ldda};
+    if ((rc = run_product(prec, LAYOUT_NT, a, es, s))) return rc;
+  }
+  if (dB) {  // dB (k x n) = A^T (k x m) * dC (m x n), A stored m x k
+    GemmArgs a{k, n, m, A, lda, dC, lddc, nullptr, nullptr, dB, lddb};
+    if ((rc = run_product(prec, LAYOUT_TN, a, es, s))) return rc;
+  }
+  return GEMM_OK;
+}
+
+}  // extern "C"

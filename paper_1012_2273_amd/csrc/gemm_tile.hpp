@@ -1,0 +1,319 @@
+// gemm_tile.hpp -- one output tile of C = op(A) * op(B) on the CDNA4 matrix
+// cores (gfx950). Shared by the single-product kernels and the persistent
+// grouped kernel.
+//
+// The product is the one of Hasta and Mutiara, Section 3.1, Algorithm 1:
+// every c[i][j] is the sum over p of a[i][p] * b[p][j], with C zeroed first
+// (Algorithms 3 and 4). Here the reduction over p is blocked into K-tiles of
+// BK and handed to MFMA instructions; the order of the partial sums differs
+// from the paper's sequential loop, the set of products does not.
+//
+// Data path of one workgroup (4 wave64s, 256 threads):
+//   HBM/L2 --16-byte vector loads--> VGPR prefetch (tile k+1)
+//   VGPR --ds_write--> LDS stage (k+1)&1     (double buffer, one barrier/tile)
+//   LDS stage k&1 --ds_read_b128--> operand fragments --> MFMA (AccVGPRs)
+//   accumulators --masked stores--> C
+//
+// LDS layout: both operands are kept "K-contiguous", X[r][0..BK) for the
+// r-th row of op(A) or the r-th column of op(B), rows padded by 16 bytes.
+// Lane group g = lane/16 of a wave owns the K sub-range [g*BK/4, (g+1)*BK/4)
+// of every K-tile and feeds it to the MFMAs in steps of KPL elements; A and
+// B use the same mapping, so each MFMA still pairs a[i][p] with b[p][j].
+//
+// Operand storage in memory (per operand, a template flag):
+//   K-contiguous  (A not transposed, or B transposed): vector loads go to LDS
+//                 unchanged;
+//   MN-contiguous (A transposed, or B not transposed): vector loads along
+//                 M (or N) are scattered into the K-contiguous LDS rows.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace g355 {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3 };
+
+// Per-precision description of the MFMA used and the element types.
+//   E    element type in global memory and LDS (bf16 kept as 16-bit pattern)
+//   Op   the per-lane operand of one MFMA
+//   Acc  the per-lane accumulator of one 16x16 output block
+//   KPL  K elements per lane per MFMA (16x16x4 -> 1, 16x16x32 -> 8)
+//   BK   K-tile depth
+//   GRP  rows per lane group in the 16x16 output block: lane l holds column
+//        l%16 and rows (q/GRP)*4*GRP + (l/16)*GRP + q%GRP, q = 0..3
+//        (binary64: rows 4q + l/16; binary32 accumulators: rows 4(l/16) + q)
+template <int P> struct Traits;
+template <> struct Traits<PREC_F64> {
+  using E = double; using Op = double; using Acc = f64x4; using Out = double;
+  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 1;
+};
+template <> struct Traits<PREC_F32> {
+  using E = float; using Op = float; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 4;
+};
+template <> struct Traits<PREC_BF16> {
+  using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4;
+};
+template <> struct Traits<PREC_SPLIT> {
+  using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 32, PLANES = 2, GRP = 4;   // hi and lo planes
+};
+
+__device__ __forceinline__ void mfma(f64x4 &acc, double a, double b) {
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mfma(f32x4 &acc, float a, float b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+__device__ __forceinline__ void mfma(f32x4 &acc, u16x8 a, u16x8 b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+
+template <typename T, int V> struct alignas(sizeof(T) * V) VecT { T e[V]; };
+
+// Arguments of one product. For PREC_SPLIT, A/B are the hi planes and
+// A2/B2 the lo planes (same leading dimensions).
+struct GemmArgs {
+  int64_t M, N, K;
+  const void *A; int64_t lda;
+  const void *B; int64_t ldb;
+  const void *A2; const void *B2;
+  void *C; int64_t ldc;
+};
+
+// Tile shape: BM x BN outputs per workgroup, WM x WN waves (64 lanes each).
+template <int BM_, int BN_, int WM_, int WN_> struct Shape {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;   // per-wave tile
+  static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 blocks per wave
+  static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "bad shape");
+};
+
+template <int P> __host__ __device__ constexpr int lds_pad() {
+  return 16 / (int)sizeof(typename Traits<P>::E);       // 16 bytes per row
+}
+template <int P, class S> __host__ __device__ constexpr int lds_bytes() {
+  using T = Traits<P>;
+  return 2 * T::PLANES * (S::BM + S::BN) * (T::BK + lds_pad<P>()) * (int)sizeof(typename T::E);
+}
+
+// Global -> VGPR -> LDS mover for one operand plane of R rows x BK.
+//   KC = true : element (r, p) at base[(r0 + r) * ld + k0 + p]
+//   KC = false: element (r, p) at base[(k0 + p) * ld + r0 + r]
+// Out-of-range elements (r0 + r >= R_total or k0 + p >= K) are loaded as 0.
+template <typename E, int R, int BK, int NT, bool KC, bool VEC>
+struct Mover {
+  static constexpr int V = VEC ? 16 / (int)sizeof(E) : 1;
+  static constexpr int NVEC = R * BK / V;
+  static constexpr int PER = (NVEC + NT - 1) / NT;
+  static constexpr bool FULL = (NVEC % NT) == 0;
+  static constexpr int LDW = BK + 16 / (int)sizeof(E);   // padded LDS row
+  using Vec = VecT<E, V>;
+
+  Vec buf[PER];
+
+  __device__ __forceinline__ static void slot(int i, int tid, int &r, int &p) {
+    const int v = tid + i * NT;
+    if constexpr (KC) { r = v / (BK / V); p = (v % (BK / V)) * V; }
+    else              { p = v / (R / V);  r = (v % (R / V)) * V; }
+  }
+
+  __device__ __forceinline__ void load(const E *__restrict__ base, int64_t ld, int64_t r0,
+                                       int64_t rtot, int64_t k0, int64_t K, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!FULL && tid + i * NT >= NVEC) continue;
+      int r, p;
+      slot(i, tid, r, p);
+      const int64_t rr = r0 + r, kk = k0 + p;
+      if constexpr (KC) {
+        const E *src = base + rr * ld + kk;
+        if (rr < rtot && kk + V <= K) {
+          buf[i] = *reinterpret_cast<const Vec *>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            buf[i].e[e] = (rr < rtot && kk + e < K) ? src[e] : E(0);
+        }
+      } else {
+        const E *src = base + kk * ld + rr;
+        if (kk < K && rr + V <= rtot) {
+          buf[i] = *reinterpret_cast<const Vec *>(src);
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e)
+            buf[i].e[e] = (kk < K && rr + e < rtot) ? src[e] : E(0);
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(E *lds, int tid) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (!FULL && tid + i * NT >= NVEC) continue;
+      int r, p;
+      slot(i, tid, r, p);
+      if constexpr (KC) {
+        *reinterpret_cast<Vec *>(lds + r * LDW + p) = buf[i];
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) lds[(r + e) * LDW + p] = buf[i].e[e];
+      }
+    }
+  }
+};
+
+// Compute one BM x BN tile of C at (m0, n0). TA: op(A) = A^T (A stored
+// K x M); TB: op(B) = B^T (B stored N x K). VEC: 16-byte loads allowed.
+template <int P, class S, bool TA, bool TB, bool VEC>
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t n0,
+                                          char *smem) {
+  using T = Traits<P>;
+  using E = typename T::E;
+  using Op = typename T::Op;
+  using Acc = typename T::Acc;
+  using Out = typename T::Out;
+  constexpr int BK = T::BK, KPL = T::KPL, PL = T::PLANES;
+  constexpr int LDW = BK + lds_pad<P>();
+  constexpr int KG = BK / 4;            // K elements per lane group per tile
+  constexpr int STEPS = KG / KPL;       // MFMA steps per K-tile
+  constexpr int NT = S::NT;
+  constexpr int A_ELEMS = S::BM * LDW, B_ELEMS = S::BN * LDW;
+  constexpr int STAGE = PL * (A_ELEMS + B_ELEMS);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % S::WM, wn = wave / S::WM;
+  const int lr = lane & 15, lgp = lane >> 4;
+
+  E *lds = reinterpret_cast<E *>(smem);
+  const E *Ap[2] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2)};
+  const E *Bp[2] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2)};
+
+  Mover<E, S::BM, BK, NT, !TA, VEC> ma[PL];
+  Mover<E, S::BN, BK, NT, TB, VEC> mb[PL];
+
+  Acc acc[S::FM][S::FN];
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
+
+  const int64_t KT = (g.K + BK - 1) / BK;
+
+  auto load_tile = [&](int64_t kt) {
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+      ma[pl].load(Ap[pl], g.lda, m0, g.M, kt * BK, g.K, tid);
+      mb[pl].load(Bp[pl], g.ldb, n0, g.N, kt * BK, g.K, tid);
+    }
+  };
+  auto store_tile = [&](int stage) {
+    E *st = lds + stage * STAGE;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+      ma[pl].store(st + pl * A_ELEMS, tid);
+      mb[pl].store(st + PL * A_ELEMS + pl * B_ELEMS, tid);
+    }
+  };
+
+  if (KT > 0) {
+    load_tile(0);
+    store_tile(0);
+  }
+  __syncthreads();
+
+  for (int64_t kt = 0; kt < KT; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < KT) load_tile(kt + 1);
+
+    const E *st = lds + cur * STAGE;
+    Op fa[PL][S::FM][STEPS], fb[PL][S::FN][STEPS];
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i) {
+        const Op *src = reinterpret_cast<const Op *>(
+            st + pl * A_ELEMS + (wm * S::WTM + i * 16 + lr) * LDW + lgp * KG);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) fa[pl][i][s] = src[s];
+      }
+#pragma unroll
+      for (int j = 0; j < S::FN; ++j) {
+        const Op *src = reinterpret_cast<const Op *>(
+            st + PL * A_ELEMS + pl * B_ELEMS + (wn * S::WTN + j * 16 + lr) * LDW + lgp * KG);
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) fb[pl][j][s] = src[s];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      if constexpr (PL == 2) {
+        // small cross terms first, then hi*hi, into one accumulator
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[1][i][s], fb[0][j][s]);
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[0][i][s], fb[1][j][s]);
+      }
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[0][i][s], fb[0][j][s]);
+    }
+
+    if (kt + 1 < KT) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds column lane%16 of each 16x16 block and the four
+  // rows given by the precision's output grouping (Traits::GRP).
+  constexpr int GRP = T::GRP;
+  Out *C = reinterpret_cast<Out *>(g.C);
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) {
+      const int64_t col = n0 + wn * S::WTN + j * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = m0 + wm * S::WTM + i * 16 + (q / GRP) * 4 * GRP + lgp * GRP + q % GRP;
+        if (row < g.M && col < g.N) C[row * g.ldc + col] = (Out)acc[i][j][q];
+      }
+    }
+  }
+}
+
+// Map a linear workgroup id onto a tile so that the workgroups one XCD
+// receives (ids x, x+8, x+16, ... go to XCD x) form one contiguous range of
+// a grouped raster: tiles that share rows of A or columns of B then share an
+// L2. `group_m` rows of tiles are walked column by column.
+__device__ __forceinline__ void tile_of(int wg, int nwg, int tiles_m, int tiles_n,
+                                        int group_m, int &tm, int &tn) {
+  constexpr int XCD = 8;
+  const int q = nwg / XCD, rem = nwg % XCD;
+  const int x = wg % XCD, j = wg / XCD;
+  const int t = x * q + (x < rem ? x : rem) + j;
+  const int per_group = group_m * tiles_n;
+  const int grp = t / per_group;
+  const int first_m = grp * group_m;
+  const int gsz = (tiles_m - first_m) < group_m ? (tiles_m - first_m) : group_m;
+  const int in = t - grp * per_group;
+  tm = first_m + in % gsz;
+  tn = in / gsz;
+}
+
+}  // namespace g355

@@ -1,0 +1,132 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device. CPU only:
+none of the calls below reaches a kernel launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1012_2273_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gemm_mi355x.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gemm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("gemm_plain", "gemm_split", "gemm_grouped", "gemm_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_texts(lib):
+    for code in range(9):
+        assert lib.gemm_strerror(code)
+    assert lib.gemm_strerror(99) == b"unknown status"
+
+
+def test_tile_config_names(lib):
+    n = lib.gemm_tile_config_count()
+    names = [lib.gemm_tile_config_name(i).decode() for i in range(n)]
+    assert names[0] == "128x128" and len(set(names)) == n
+    assert lib.gemm_tile_config_name(n) == b""
+    assert lib.gemm_plain_force_config(n) == _lib.GEMM_EINVAL
+    assert lib.gemm_plain_force_config(-1) == _lib.GEMM_OK
+
+
+def _plain(lib, dtype=0, m=4, n=4, k=4, A=16, lda=4, B=16, ldb=4, C=16, ldc=4):
+    v = lambda x: ctypes.c_void_p(x) if x else None
+    return lib.gemm_plain(dtype, m, n, k, v(A), lda, v(B), ldb, v(C), ldc, None)
+
+
+def test_plain_validation(lib):
+    assert _plain(lib, dtype=7) == _lib.GEMM_EUNSUPPORTED
+    assert _plain(lib, m=-1) == _lib.GEMM_EINVAL
+    assert _plain(lib, k=-3) == _lib.GEMM_EINVAL
+    assert _plain(lib, A=0) == _lib.GEMM_ENULL
+    assert _plain(lib, C=0) == _lib.GEMM_ENULL
+    assert _plain(lib, lda=3) == _lib.GEMM_ELD
+    assert _plain(lib, ldb=2) == _lib.GEMM_ELD
+    assert _plain(lib, ldc=1) == _lib.GEMM_ELD
+    assert b"leading dimension" in lib.gemm_last_error()
+    # empty output: no work, no device call
+    assert _plain(lib, m=0, A=0, C=0) == _lib.GEMM_OK
+    assert _plain(lib, n=0, B=0, C=0, ldb=0, ldc=0) == _lib.GEMM_OK
+
+
+def test_split_workspace_size(lib):
+    assert lib.gemm_split_workspace_size(-1, 2, 2) == 0
+    s = lib.gemm_split_workspace_size(2000, 2000, 2000)
+    assert s >= 2 * 2 * 2000 * 2000 * 2 and s % 256 == 0
+    # k padded to 8 elements per plane row
+    assert lib.gemm_split_workspace_size(1, 1, 1) == 4 * 256
+
+
+def test_split_validation(lib):
+    v = ctypes.c_void_p
+    ws = lib.gemm_split_workspace_size(8, 8, 8)
+    assert lib.gemm_split(8, 8, 8, v(16), 8, v(16), 8, v(16), 8, None, ws, None) == _lib.GEMM_EWORKSPACE
+    assert lib.gemm_split(8, 8, 8, v(16), 8, v(16), 8, v(16), 8, v(256), ws - 1, None) == _lib.GEMM_EWORKSPACE
+    assert lib.gemm_split(8, 8, 8, v(16), 8, v(16), 8, v(16), 8, v(8), ws, None) == _lib.GEMM_EWORKSPACE
+    assert lib.gemm_split(8, 8, 8, v(16), 7, v(16), 8, v(16), 8, v(256), ws, None) == _lib.GEMM_ELD
+    assert lib.gemm_split(8, -8, 8, v(16), 8, v(16), 8, v(16), 8, v(256), ws, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_split_convert(4, 4, v(16), 4, 2, v(16), v(16), 4, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_split_convert(4, 5, v(16), 5, 1, v(16), v(16), 3, None) == _lib.GEMM_ELD
+    assert lib.gemm_split_convert(4, 5, v(16), 5, 0, None, v(16), 5, None) == _lib.GEMM_ENULL
+
+
+def test_backward_validation(lib):
+    v = ctypes.c_void_p
+    assert lib.gemm_backward(5, 4, 4, 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, None) == _lib.GEMM_EUNSUPPORTED
+    assert lib.gemm_backward(0, 4, 4, 4, v(16), 4, v(16), 4, None, 4, v(16), 4, v(16), 4, None) == _lib.GEMM_ENULL
+    assert lib.gemm_backward(0, 4, 4, 4, v(16), 4, v(16), 3, v(16), 4, v(16), 4, None, 0, None) == _lib.GEMM_ELD
+    assert lib.gemm_backward(0, 4, 4, 4, v(16), 3, v(16), 4, v(16), 4, None, 0, v(16), 4, None) == _lib.GEMM_ELD
+    assert lib.gemm_backward(0, 4, -1, 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, None) == _lib.GEMM_EINVAL
+
+
+def test_grouped_validation(lib):
+    h = ctypes.c_void_p()
+    P = _lib.GemmProblem
+    arr = (P * 2)(P(4, 4, 4, 16, 16, 16, 4, 4, 4), P(4, 4, 4, 16, 16, 16, 3, 4, 4))
+    assert lib.gemm_grouped_plan_create(ctypes.byref(h), 0, arr, 2, None, 0, None) == _lib.GEMM_ELD
+    assert b"problem 1" in lib.gemm_last_error()
+    assert lib.gemm_grouped_plan_create(ctypes.byref(h), 2, arr, 2, None, 0, None) == _lib.GEMM_EUNSUPPORTED
+    assert lib.gemm_grouped_plan_create(ctypes.byref(h), 0, arr, -1, None, 0, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_grouped_plan_create(ctypes.byref(h), 0, arr, 1, None, 8, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_grouped_plan_create(None, 0, arr, 1, None, 0, None) == _lib.GEMM_ENULL
+    arr2 = (P * 1)(P(4, 4, 4, 16, None, 16, 4, 4, 4))
+    assert lib.gemm_grouped_plan_create(ctypes.byref(h), 0, arr2, 1, None, 0, None) == _lib.GEMM_ENULL
+    assert lib.gemm_grouped_run(None, None) == _lib.GEMM_ENULL
+    assert lib.gemm_grouped_plan_destroy(None) == _lib.GEMM_OK
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports, links or reads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1012_2273_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text and "oracle.c" not in text, f

@@ -1,0 +1,165 @@
+"""GPU parity of the persistent grouped product (captured hipGraph, tuned policy).
+
+512 independent square products, N log-uniform in [10, 2000], in binary64
+and binary32. Every problem equals the single-product kernel at the same
+tile shape bit for bit (same tiles, same reduction order), and the oracle
+checks every problem (full product for N <= 256, sampled entries above).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1012_2273_amd import inputs
+from gpu_util import dev, sample_idx, say
+
+pytestmark = pytest.mark.gpu
+CLASS_EDGES = [48, 96, 192, 384, 768, 1536]
+
+
+def size_class(m, n):
+    s = max(m, n)
+    return sum(1 for e in CLASS_EDGES if s >= e)
+
+
+@pytest.fixture(scope="module")
+def G(gpu_device):
+    import paper_1012_2273_amd as G
+    G.load()
+    yield G
+    G.force_tile_config(-1)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _batch(count, dtype, seed=3_000_000):
+    sizes = inputs.batch_sizes(count, seed)
+    probs = [inputs.batch_problem(i, int(n), seed, dtype) for i, n in enumerate(sizes)]
+    return sizes, probs
+
+
+def _check_against_oracle(sizes, probs, Cs, tol, max_full=256):
+    worst = 0.0
+    for i, (n, (A, B)) in enumerate(zip(sizes, probs)):
+        C = Cs[i].cpu().double().numpy()
+        if n <= max_full:
+            err = oracle.relerr_fro(C, oracle.gemm(A, B))
+        else:
+            r, c = sample_idx(n, n, 120, i)
+            err = oracle.relerr_sampled(C[r, c], oracle.gemm_entries(A, B, r, c))
+        worst = max(worst, err)
+    assert worst <= tol, worst
+    return worst
+
+
+@pytest.mark.parametrize("tname", ["f64", "f32"])
+def test_batch_512_graph_autotuned(G, tname, tmp_path):
+    torch = _torch()
+    dt = np.float64 if tname == "f64" else np.float32
+    tol = 1e-12 if tname == "f64" else 1e-5
+    sizes, probs = _batch(512, dt)
+    say(f"grouped {tname}: sum 2N^3 = {sum(2 * int(n) ** 3 for n in sizes):.3e}")
+    As = [dev(A, torch) for A, _ in probs]
+    Bs = [dev(B, torch) for _, B in probs]
+    cache = str(tmp_path / "tune.json")
+    plan = G.GroupedPlan(As, Bs, autotune=True, tune_cache=cache)
+    tiles, policy = plan.info()
+    say(f"grouped {tname}: tiles={tiles} policy={policy}")
+    assert os.path.exists(cache)
+    Cs = plan.run()
+    torch.cuda.synchronize()
+    worst = _check_against_oracle(sizes, probs, Cs, tol)
+    say(f"grouped {tname}: worst relerr={worst:.3e}")
+
+    # bitwise equal to single-product launches at the policy's tile shape
+    names = G.tile_configs()
+    for i in range(0, 512, 7):
+        cfg = names.index(policy[size_class(int(sizes[i]), int(sizes[i]))])
+        G.force_tile_config(cfg)
+        Ci = G.gemm_plain(As[i], Bs[i])
+        G.force_tile_config(-1)
+        torch.cuda.synchronize()
+        assert torch.equal(Ci, Cs[i]), i
+
+    # graph replays with eager work in between: every replay identical
+    first = [C.clone() for C in Cs]
+    for rep in range(6):
+        for C in Cs:
+            C.zero_()
+        _ = G.gemm_plain(As[0], Bs[0])
+        plan.run()
+        torch.cuda.synchronize()
+        for i in range(0, 512, 5):
+            assert torch.equal(Cs[i], first[i]), (rep, i)
+
+    # a second plan reads the tuned policy from the cache
+    plan2 = G.GroupedPlan(As[:512], Bs[:512], autotune=True, tune_cache=cache)
+    assert plan2.info()[1] == policy
+    plan2.close()
+    plan.close()
+
+
+def test_plan_update_new_pointers(G):
+    torch = _torch()
+    sizes, probs = _batch(40, np.float64, seed=77)
+    As = [dev(A, torch) for A, _ in probs]
+    Bs = [dev(B, torch) for _, B in probs]
+    plan = G.GroupedPlan(As, Bs)
+    plan.run()
+    As2 = [A.flip(0).contiguous() for A in As]
+    Cs2 = [torch.empty_like(C) for C in plan.Cs]
+    plan.update(As2, Bs, Cs2)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(probs):
+        ref = oracle.gemm(A[::-1].copy(), B) if sizes[i] <= 300 else None
+        if ref is not None:
+            assert oracle.relerr_fro(Cs2[i].cpu().numpy(), ref) <= 1e-12
+    with pytest.raises(ValueError):
+        plan.update(As2[:-1], Bs[:-1], Cs2[:-1])
+    plan.close()
+
+
+def test_uncaptured_and_edge_problems(G):
+    torch = _torch()
+    shapes = [(5, 7, 3), (0, 4, 4), (6, 0, 2), (9, 9, 0), (1, 1, 1), (130, 70, 257), (33, 600, 10)]
+    As, Bs, hostA, hostB = [], [], [], []
+    for m, n, k in shapes:
+        A, B = inputs.uniform_mnk(m, n, k, m + n + k)
+        hostA.append(A)
+        hostB.append(B)
+        As.append(dev(A, torch))
+        Bs.append(dev(B, torch))
+    Cs = [torch.full((m, n), 3.0, dtype=torch.float64, device="cuda:0") for m, n, _ in shapes]
+    G.gemm_grouped(As, Bs, Cs)
+    for (m, n, k), A, B, C in zip(shapes, hostA, hostB, Cs):
+        got = C.cpu().numpy()
+        if m == 0 or n == 0:
+            assert got.size == 0
+        elif k == 0:
+            assert np.count_nonzero(got) == 0
+        else:
+            assert oracle.relerr_fro(got, oracle.gemm(A, B)) <= 1e-12
+    # empty group
+    G.gemm_grouped([], [], [])
+
+
+def test_grouped_integer_bit_exact(G):
+    torch = _torch()
+    sizes = inputs.batch_sizes(64, 11, lo=10, hi=700)
+    As, Bs, probs = [], [], []
+    for i, n in enumerate(sizes):
+        A, B = inputs.integers((int(n), int(n)), 100 + i, np.float32, 2)
+        probs.append((A, B))
+        As.append(dev(A, torch))
+        Bs.append(dev(B, torch))
+    plan = G.GroupedPlan(As, Bs)
+    Cs = plan.run()
+    torch.cuda.synchronize()
+    for (A, B), C in zip(probs, Cs):
+        assert np.array_equal(C.cpu().double().numpy(), oracle.gemm(A, B))
+    plan.close()
