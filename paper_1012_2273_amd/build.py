@@ -29,6 +29,10 @@ CFLAGS = [
     # keep the compiler from forming packed binary32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
+    # MFMA accumulators in architectural VGPRs: on gfx950 a binary64 MFMA that
+    # writes AccVGPRs issues at about half rate (measured: ~138 vs 64 cycles
+    # per v_mfma_f64_16x16x4 per wave)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 
@@ -49,7 +53,7 @@ def _stale(target, deps):
 
 def _compile(src, force):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if force or _stale(obj, [src, *_headers()]):
+    if force or _stale(obj, [src, *_headers(), os.path.abspath(__file__)]):
         cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:

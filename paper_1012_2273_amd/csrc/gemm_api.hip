@@ -81,8 +81,22 @@ static size_t esize_of(int dtype) {
   return 0;
 }
 
-static bool aligned16(const void *p, int64_t ld, size_t es) {
-  return ((uintptr_t)p % 16 == 0) && (((uint64_t)ld * es) % 16 == 0);
+// 16-byte vector loads need an aligned base and row pitch, and a contiguous
+// extent that is a whole number of vectors (every vector is then entirely
+// inside or outside the matrix).
+static bool vec_ok(const void *p, int64_t ld, size_t es, int64_t contiguous_extent) {
+  const int64_t v = 16 / (int64_t)es;
+  return ((uintptr_t)p % 16 == 0) && (((uint64_t)ld * es) % 16 == 0) &&
+         (contiguous_extent % v == 0);
+}
+
+// Operand offsets inside a tile are 32-bit: 128 rows of ld elements must
+// span less than 2^31 bytes.
+static int check_ld_range(const char *name, int64_t ld, size_t es) {
+  if ((uint64_t)ld * es >= (1ull << 24))
+    return set_error(GEMM_EINVAL, std::string("leading dimension of ") + name +
+                                      " too large (row pitch must be below 16 MiB)");
+  return GEMM_OK;
 }
 
 static int hip_fail(hipError_t e, const char *what) {
@@ -101,9 +115,13 @@ static int check_mat(const char *name, const void *p, int64_t rows, int64_t cols
 
 static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hipStream_t s) {
   if (a.M == 0 || a.N == 0) return GEMM_OK;
+  int rc;
+  if ((rc = check_ld_range("A", a.lda, es_in)) || (rc = check_ld_range("B", a.ldb, es_in)))
+    return rc;
   const int cfg = choose_cfg(prec, a.M, a.N);
-  bool vec = aligned16(a.A, a.lda, es_in) && aligned16(a.B, a.ldb, es_in);
-  if (prec == PREC_SPLIT) vec = true;
+  const bool ta = layout == LAYOUT_TN, tb = layout == LAYOUT_NT;
+  bool vec = vec_ok(a.A, a.lda, es_in, ta ? a.M : a.K) && vec_ok(a.B, a.ldb, es_in, tb ? a.K : a.N);
+  if (prec == PREC_SPLIT) vec = true;   // planes are padded to whole vectors
   hipError_t e = launch_plain(prec, layout, cfg, vec, a, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return GEMM_OK;
@@ -198,7 +216,9 @@ int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx, 
   const int64_t out_cols = transpose ? rows : cols;
   if (ldo < out_cols) return set_error(GEMM_ELD, "ldo smaller than the plane row length");
   if (rows == 0 || cols == 0) return GEMM_OK;
-  hipError_t e = launch_split(rows, cols, X, ldx, transpose != 0, hi, lo, ldo, (hipStream_t)stream);
+  if ((rc = check_ld_range("X", ldx, 4))) return rc;
+  hipError_t e = launch_split(rows, cols, X, ldx, transpose != 0, hi, lo, ldo,
+                              transpose ? rows : cols, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "split launch");
   return GEMM_OK;
 }
@@ -226,11 +246,14 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
   uint16_t *ahi = (uint16_t *)(ws + off[0]), *alo = (uint16_t *)(ws + off[1]);
   uint16_t *bhi = (uint16_t *)(ws + off[2]), *blo = (uint16_t *)(ws + off[3]);
   if (k > 0) {
-    hipError_t e = launch_split(m, k, A, lda, false, ahi, alo, kp, s);
-    if (e == hipSuccess) e = launch_split(k, n, B, ldb, true, bhi, blo, kp, s);
+    // planes carry zeros in the padding columns [k, kp), so the product may
+    // run over kp (a whole number of 8-element vectors) unchanged
+    if ((rc = check_ld_range("A", lda, 4)) || (rc = check_ld_range("B", ldb, 4))) return rc;
+    hipError_t e = launch_split(m, k, A, lda, false, ahi, alo, kp, kp, s);
+    if (e == hipSuccess) e = launch_split(k, n, B, ldb, true, bhi, blo, kp, kp, s);
     if (e != hipSuccess) return hip_fail(e, "split launch");
   }
-  GemmArgs a{m, n, k, ahi, kp, bhi, kp, alo, blo, C, ldc};
+  GemmArgs a{m, n, k > 0 ? kp : 0, ahi, kp, bhi, kp, alo, blo, C, ldc};
   return run_product(PREC_SPLIT, LAYOUT_NT, a, 2, s);
 }
 

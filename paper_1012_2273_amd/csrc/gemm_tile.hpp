@@ -106,10 +106,41 @@ template <int P, class S> __host__ __device__ constexpr int lds_bytes() {
   return 2 * T::PLANES * (S::BM + S::BN) * (T::BK + lds_pad<P>()) * (int)sizeof(typename T::E);
 }
 
+// Buffer resource over `base` for raw buffer loads (CDNA: 32-bit data
+// format in word 3). Offsets at or above kOob read as zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, 0x7fffffff,
+                                           0x00020000);
+}
+constexpr uint32_t kOob = 0x80000000u;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int BYTES> struct RawT;
+template <> struct RawT<16> { using T = u32x4; };
+template <> struct RawT<8> { using T = u32x2; };
+template <> struct RawT<4> { using T = uint32_t; };
+template <> struct RawT<2> { using T = uint16_t; };
+
+template <int BYTES>
+__device__ __forceinline__ typename RawT<BYTES>::T raw_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (BYTES == 16) return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  else if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  else if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  else return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+
 // Global -> VGPR -> LDS mover for one operand plane of R rows x BK.
 //   KC = true : element (r, p) at base[(r0 + r) * ld + k0 + p]
 //   KC = false: element (r, p) at base[(k0 + p) * ld + r0 + r]
-// Out-of-range elements (r0 + r >= R_total or k0 + p >= K) are loaded as 0.
+// Each thread moves whole vectors of V elements along the contiguous
+// direction. The host enables V > 1 only when every vector is entirely
+// inside or entirely outside the matrix (16-byte aligned base and ld, and the
+// contiguous extent a multiple of V); an outside vector gets the offset kOob
+// and the buffer unit returns zeros, so the tile edges need no branches.
+// Offsets are 32-bit byte offsets from the K-tile's base: R * ld * sizeof(E)
+// must stay below 2^31 (the host checks).
 template <typename E, int R, int BK, int NT, bool KC, bool VEC>
 struct Mover {
   static constexpr int V = VEC ? 16 / (int)sizeof(E) : 1;
@@ -117,9 +148,11 @@ struct Mover {
   static constexpr int PER = (NVEC + NT - 1) / NT;
   static constexpr bool FULL = (NVEC % NT) == 0;
   static constexpr int LDW = BK + 16 / (int)sizeof(E);   // padded LDS row
-  using Vec = VecT<E, V>;
+  using Raw = typename RawT<V * (int)sizeof(E)>::T;
 
-  Vec buf[PER];
+  Raw buf[PER];
+  uint32_t off[PER];    // byte offset of the slot within a K-tile
+  bool rok[PER];        // the slot's row (M or N index) is inside the matrix
 
   __device__ __forceinline__ static void slot(int i, int tid, int &r, int &p) {
     const int v = tid + i * NT;
@@ -127,33 +160,27 @@ struct Mover {
     else              { p = v / (R / V);  r = (v % (R / V)) * V; }
   }
 
-  __device__ __forceinline__ void load(const E *__restrict__ base, int64_t ld, int64_t r0,
-                                       int64_t rtot, int64_t k0, int64_t K, int tid) {
+  __device__ __forceinline__ void init(int64_t ld, int64_t r0, int64_t rtot, int tid) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      if (!FULL && tid + i * NT >= NVEC) continue;
       int r, p;
       slot(i, tid, r, p);
-      const int64_t rr = r0 + r, kk = k0 + p;
-      if constexpr (KC) {
-        const E *src = base + rr * ld + kk;
-        if (rr < rtot && kk + V <= K) {
-          buf[i] = *reinterpret_cast<const Vec *>(src);
-        } else {
+      const bool live = FULL || (tid + i * NT < NVEC);
+      rok[i] = live && (r0 + r < rtot);
+      if constexpr (KC) off[i] = (uint32_t)(((int64_t)r * ld + p) * (int64_t)sizeof(E));
+      else              off[i] = (uint32_t)(((int64_t)p * ld + r) * (int64_t)sizeof(E));
+    }
+  }
+
+  // tile_base: element (r0, k0) for KC, (k0, r0) otherwise.
+  __device__ __forceinline__ void load(const E *tile_base, int64_t k0, int64_t K, int tid) {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(tile_base);
 #pragma unroll
-          for (int e = 0; e < V; ++e)
-            buf[i].e[e] = (rr < rtot && kk + e < K) ? src[e] : E(0);
-        }
-      } else {
-        const E *src = base + kk * ld + rr;
-        if (kk < K && rr + V <= rtot) {
-          buf[i] = *reinterpret_cast<const Vec *>(src);
-        } else {
-#pragma unroll
-          for (int e = 0; e < V; ++e)
-            buf[i].e[e] = (kk < K && rr + e < rtot) ? src[e] : E(0);
-        }
-      }
+    for (int i = 0; i < PER; ++i) {
+      int r, p;
+      slot(i, tid, r, p);
+      const bool ok = rok[i] && (k0 + p < K);
+      buf[i] = raw_load<V * (int)sizeof(E)>(rs, ok ? off[i] : kOob);
     }
   }
 
@@ -164,10 +191,11 @@ struct Mover {
       int r, p;
       slot(i, tid, r, p);
       if constexpr (KC) {
-        *reinterpret_cast<Vec *>(lds + r * LDW + p) = buf[i];
+        *reinterpret_cast<Raw *>(lds + r * LDW + p) = buf[i];
       } else {
+        const VecT<E, V> v = __builtin_bit_cast(VecT<E, V>, buf[i]);
 #pragma unroll
-        for (int e = 0; e < V; ++e) lds[(r + e) * LDW + p] = buf[i].e[e];
+        for (int e = 0; e < V; ++e) lds[(r + e) * LDW + p] = v.e[e];
       }
     }
   }
@@ -211,11 +239,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
 
   const int64_t KT = (g.K + BK - 1) / BK;
 
+#pragma unroll
+  for (int pl = 0; pl < PL; ++pl) {
+    ma[pl].init(g.lda, m0, g.M, tid);
+    mb[pl].init(g.ldb, n0, g.N, tid);
+  }
   auto load_tile = [&](int64_t kt) {
+    const int64_t k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
-      ma[pl].load(Ap[pl], g.lda, m0, g.M, kt * BK, g.K, tid);
-      mb[pl].load(Bp[pl], g.ldb, n0, g.N, kt * BK, g.K, tid);
+      const E *ta = TA ? Ap[pl] + k0 * g.lda + m0 : Ap[pl] + m0 * g.lda + k0;
+      const E *tb = TB ? Bp[pl] + n0 * g.ldb + k0 : Bp[pl] + k0 * g.ldb + n0;
+      ma[pl].load(ta, k0, g.K, tid);
+      mb[pl].load(tb, k0, g.K, tid);
     }
   };
   auto store_tile = [&](int stage) {

@@ -279,6 +279,9 @@ static int validate_problems(int dtype, const gemm_problem *probs, int32_t count
     }
     if (q.lda < q.k || q.ldb < q.n || q.ldc < q.n)
       return set_error(GEMM_ELD, "leading dimension too small" + at);
+    const uint64_t es = dtype == GEMM_F64 ? 8 : 4;
+    if ((uint64_t)q.lda * es >= (1ull << 24) || (uint64_t)q.ldb * es >= (1ull << 24))
+      return set_error(GEMM_EINVAL, "leading dimension too large (row pitch must be below 16 MiB)" + at);
   }
   return GEMM_OK;
 }
@@ -288,8 +291,12 @@ static GroupedProblem to_device(const gemm_problem &q, size_t es) {
   d.M = q.m; d.N = q.n; d.K = q.k;
   d.A = q.A; d.B = q.B; d.C = q.C;
   d.lda = q.lda; d.ldb = q.ldb; d.ldc = q.ldc;
+  // 16-byte loads: aligned bases and pitches, and K (A rows) and N (B rows)
+  // whole numbers of vectors
+  const int64_t v = 16 / (int64_t)es;
   d.vec = ((uintptr_t)q.A % 16 == 0) && ((uintptr_t)q.B % 16 == 0) &&
-          ((uint64_t)q.lda * es % 16 == 0) && ((uint64_t)q.ldb * es % 16 == 0);
+          ((uint64_t)q.lda * es % 16 == 0) && ((uint64_t)q.ldb * es % 16 == 0) &&
+          (q.k % v == 0) && (q.n % v == 0);
   d.pad_ = 0;
   return d;
 }

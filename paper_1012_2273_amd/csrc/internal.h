@@ -27,9 +27,12 @@ enum Layout : int { LAYOUT_NN = 0, LAYOUT_NT = 1, LAYOUT_TN = 2 };
 hipError_t launch_plain(int prec, int layout, int cfg, bool vec, const GemmArgs &a,
                         hipStream_t stream);
 
-// Split kernels: X (rows x cols, ldx) -> hi/lo 16-bit planes.
+// Split kernels: X (rows x cols, ldx) -> hi/lo 16-bit planes. Plane rows
+// are written up to `out_pad` >= their length (cols, or rows when
+// transposed), the padding with zeros.
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, bool transpose,
-                        uint16_t *hi, uint16_t *lo, int64_t ldo, hipStream_t stream);
+                        uint16_t *hi, uint16_t *lo, int64_t ldo, int64_t out_pad,
+                        hipStream_t stream);
 
 // Grouped: descriptors and tile-queue items live in device memory.
 struct GroupedProblem {          // device-side problem record

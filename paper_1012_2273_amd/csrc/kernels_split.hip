@@ -22,13 +22,15 @@ __device__ __forceinline__ void split1(float x, uint16_t &h, uint16_t &l) {
   l = __builtin_bit_cast(uint16_t, (__bf16)r);
 }
 
-// Same orientation: (rows x cols) -> (rows x cols). One thread per 4
-// consecutive elements of a row; VEC: X rows and planes are 16/8-byte aligned.
+// Same orientation: (rows x cols) -> (rows x cols_pad), zeros in [cols,
+// cols_pad). One thread per 4 consecutive elements of a plane row; VEC: X
+// rows and planes are 16/8-byte aligned.
 template <bool VEC>
 __global__ void __launch_bounds__(256)
 split_rows_kernel(int64_t rows, int64_t cols, const float *__restrict__ X, int64_t ldx,
-                  uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldo) {
-  const int64_t cq = (cols + 3) / 4;
+                  uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldo,
+                  int64_t cols_pad) {
+  const int64_t cq = (cols_pad + 3) / 4;
   const int64_t total = rows * cq;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -42,15 +44,24 @@ split_rows_kernel(int64_t rows, int64_t cols, const float *__restrict__ X, int64
       *reinterpret_cast<uint2 *>(dh) = make_uint2(h0 | ((uint32_t)h1 << 16), h2 | ((uint32_t)h3 << 16));
       *reinterpret_cast<uint2 *>(dl) = make_uint2(l0 | ((uint32_t)l1 << 16), l2 | ((uint32_t)l3 << 16));
     } else {
-      for (int e = 0; e < 4 && c + e < cols; ++e) split1(src[e], dh[e], dl[e]);
+      for (int e = 0; e < 4 && c + e < cols_pad; ++e) {
+        if (c + e < cols) {
+          split1(src[e], dh[e], dl[e]);
+        } else {
+          dh[e] = 0;
+          dl[e] = 0;
+        }
+      }
     }
   }
 }
 
-// Transposing: (rows x cols) -> planes of (cols x rows): out[c][r].
+// Transposing: (rows x cols) -> planes of (cols x rows_pad): out[c][r],
+// zeros for r in [rows, rows_pad).
 __global__ void __launch_bounds__(256)
 split_transpose_kernel(int64_t rows, int64_t cols, const float *__restrict__ X, int64_t ldx,
-                       uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldo) {
+                       uint16_t *__restrict__ hi, uint16_t *__restrict__ lo, int64_t ldo,
+                       int64_t rows_pad) {
   constexpr int T = 64, PITCH = T + 2;
   __shared__ uint16_t sh[2][T][PITCH];
   const int64_t tiles_c = (cols + T - 1) / T;
@@ -71,7 +82,7 @@ split_transpose_kernel(int64_t rows, int64_t cols, const float *__restrict__ X, 
   for (int i = 0; i < T * T / 256; ++i) {
     const int idx = tid + i * 256;
     const int oc = idx / T, orr = idx % T;      // output row = input column
-    if (c0 + oc < cols && r0 + orr < rows) {
+    if (c0 + oc < cols && r0 + orr < rows_pad) {
       hi[(c0 + oc) * ldo + r0 + orr] = sh[0][orr][oc];
       lo[(c0 + oc) * ldo + r0 + orr] = sh[1][orr][oc];
     }
@@ -79,25 +90,26 @@ split_transpose_kernel(int64_t rows, int64_t cols, const float *__restrict__ X, 
 }
 
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, bool transpose,
-                        uint16_t *hi, uint16_t *lo, int64_t ldo, hipStream_t stream) {
+                        uint16_t *hi, uint16_t *lo, int64_t ldo, int64_t out_pad,
+                        hipStream_t stream) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   if (transpose) {
-    const int64_t tiles = ((rows + 63) / 64) * ((cols + 63) / 64);
+    const int64_t tiles = ((out_pad + 63) / 64) * ((cols + 63) / 64);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(split_transpose_kernel, dim3((unsigned)tiles), dim3(256), 0, stream,
-                       rows, cols, X, ldx, hi, lo, ldo);
+                       rows, cols, X, ldx, hi, lo, ldo, out_pad);
   } else {
     const bool vec = ((uintptr_t)X % 16 == 0) && (ldx % 4 == 0) && ((uintptr_t)hi % 8 == 0) &&
                      ((uintptr_t)lo % 8 == 0) && (ldo % 4 == 0);
-    const int64_t work = rows * ((cols + 3) / 4);
+    const int64_t work = rows * ((out_pad + 3) / 4);
     int64_t blocks = (work + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (vec)
       hipLaunchKernelGGL(split_rows_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream,
-                         rows, cols, X, ldx, hi, lo, ldo);
+                         rows, cols, X, ldx, hi, lo, ldo, out_pad);
     else
       hipLaunchKernelGGL(split_rows_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream,
-                         rows, cols, X, ldx, hi, lo, ldo);
+                         rows, cols, X, ldx, hi, lo, ldo, out_pad);
   }
   return hipGetLastError();
 }
