@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a device-to-device copy of 512 MiB (3 times) so that "
+                         "counter runs can scale FETCH_SIZE/WRITE_SIZE to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has "
@@ -156,6 +159,16 @@ def main():
         work["grouped"] = (plan.run, float(sum(2 * int(n) ** 3 for n in sizes)))
 
     order = [p for p in ALL_PATHS if p in paths]
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes 512 MiB each
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 512 MiB device-to-device copies")
+        del src, dst
 
     # ---------------------------------------------------------------- timing
     stream = torch.cuda.current_stream(dev)

@@ -28,8 +28,9 @@ int set_error(int code, const std::string &detail) {
 }
 void clear_error() { t_err.clear(); }
 
-static const CfgInfo kCfgs[CFG_COUNT] = {
-    {128, 128, "128x128"}, {128, 64, "128x64"}, {64, 64, "64x64"}, {32, 32, "32x32"}};
+static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x64"},
+                                         {64, 64, "64x64"},     {32, 32, "32x32"},
+                                         {128, 128, "128x128w8"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
@@ -57,8 +58,8 @@ static int device_cus() {
 static int choose_cfg(int prec, int64_t m, int64_t n) {
   const int forced = g_force_cfg.load();
   if (forced >= 0 && forced < CFG_COUNT) return forced;
-  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6};
-  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35};
+  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6, 0.98};
+  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35, 0.98};
   const double *eff = (prec == PREC_F64) ? eff_f64 : eff_lp;
   const int64_t cus = device_cus();
   int best = CFG_128x128;

@@ -179,7 +179,7 @@ static std::string cache_key(const gemm_plan &p) {
 static bool policy_valid(const std::vector<int> &v) {
   if ((int)v.size() != NCLASS) return false;
   for (int x : v)
-    if (x < 0 || x >= CFG_COUNT) return false;
+    if (x < 0 || x >= CFG_GROUPED_COUNT) return false;
   return true;
 }
 
@@ -218,7 +218,7 @@ static int autotune(gemm_plan &p, hipStream_t s, int *policy) {
   if (rc) return rc;
   for (int c = NCLASS - 1; c >= 0; --c) {
     if (!present[c]) continue;
-    for (int cfg = 0; cfg < CFG_COUNT; ++cfg) {
+    for (int cfg = 0; cfg < CFG_GROUPED_COUNT; ++cfg) {
       if (cfg == policy[c]) continue;
       int trial[NCLASS];
       std::memcpy(trial, policy, sizeof(trial));
@@ -331,7 +331,7 @@ int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *pro
     p->dprob_host[i] = to_device(probs[i], es);
     if (probs[i].m > 0 && probs[i].n > 0) {
       int64_t worst = 0;   // most tiles any configuration can produce
-      for (int c = 0; c < CFG_COUNT; ++c) {
+      for (int c = 0; c < CFG_GROUPED_COUNT; ++c) {
         const CfgInfo &ci = cfg_info(c);
         worst = std::max(worst, ((probs[i].m + ci.bm - 1) / ci.bm) * ((probs[i].n + ci.bn - 1) / ci.bn));
       }

@@ -14,7 +14,12 @@ struct GemmArgs;
 
 // Tile configurations the kernels are instantiated for. The id is the
 // value the tuner and the grouped planner store.
-enum TileCfg : int { CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3, CFG_COUNT = 4 };
+// Configs below CFG_GROUPED_COUNT use 256 threads and can share the
+// persistent grouped kernel; the others run as single-product launches.
+enum TileCfg : int {
+  CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3, CFG_GROUPED_COUNT = 4,
+  CFG_128x128_W8 = 4, CFG_COUNT = 5
+};
 struct CfgInfo { int bm, bn; const char *name; };
 const CfgInfo &cfg_info(int id);
 

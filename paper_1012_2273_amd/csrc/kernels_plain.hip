@@ -52,6 +52,7 @@ using S128x128 = Shape<128, 128, 2, 2>;
 using S128x64 = Shape<128, 64, 2, 2>;
 using S64x64 = Shape<64, 64, 2, 2>;
 using S32x32 = Shape<32, 32, 2, 2>;
+using S128x128w8 = Shape<128, 128, 4, 2>;
 
 template <int P>
 static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipStream_t s) {
@@ -60,6 +61,7 @@ static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipSt
     case CFG_128x64: return by_layout<P, S128x64>(layout, vec, a, s);
     case CFG_64x64: return by_layout<P, S64x64>(layout, vec, a, s);
     case CFG_32x32: return by_layout<P, S32x32>(layout, vec, a, s);
+    case CFG_128x128_W8: return by_layout<P, S128x128w8>(layout, vec, a, s);
   }
   return hipErrorInvalidValue;
 }
