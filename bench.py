@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    ap.add_argument("--tile-config", type=int, default=-1,
+                    help="force one tile configuration id for single-product launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device-to-device copy of 512 MiB (3 times) so that "
                          "counter runs can scale FETCH_SIZE/WRITE_SIZE to bytes")
@@ -102,6 +104,8 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     G.load()
+    if args.tile_config >= 0:
+        G.force_tile_config(args.tile_config)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     N = args.n

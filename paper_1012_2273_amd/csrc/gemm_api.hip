@@ -30,10 +30,19 @@ void clear_error() { t_err.clear(); }
 
 static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x64"},
                                          {64, 64, "64x64"},     {32, 32, "32x32"},
-                                         {128, 128, "128x128w8"}};
+                                         {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
+                                         {128, 64, "128x64k2"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
+
+// The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
+// paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
+bool cfg_supported(int prec, int cfg) {
+  if (cfg < 0 || cfg >= CFG_COUNT) return false;
+  if (cfg == CFG_128x128_K2 || cfg == CFG_128x64_K2) return prec == PREC_F64 || prec == PREC_F32;
+  return true;
+}
 
 static int device_cus() {
   static std::mutex mu;
@@ -57,14 +66,15 @@ static int device_cus() {
 // fill the 256 CUs when C is small.
 static int choose_cfg(int prec, int64_t m, int64_t n) {
   const int forced = g_force_cfg.load();
-  if (forced >= 0 && forced < CFG_COUNT) return forced;
-  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6, 0.98};
-  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35, 0.98};
+  if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced)) return forced;
+  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6, 0.98, 0.99, 0.9};
+  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35, 0.98, 0.99, 0.85};
   const double *eff = (prec == PREC_F64) ? eff_f64 : eff_lp;
   const int64_t cus = device_cus();
   int best = CFG_128x128;
   double best_cost = 0;
   for (int c = 0; c < CFG_COUNT; ++c) {
+    if (!cfg_supported(prec, c)) continue;
     const int64_t tiles = ((m + kCfgs[c].bm - 1) / kCfgs[c].bm) * ((n + kCfgs[c].bn - 1) / kCfgs[c].bn);
     const int64_t waves = (tiles + cus - 1) / cus;
     const double cost = (double)waves * kCfgs[c].bm * kCfgs[c].bn / eff[c];

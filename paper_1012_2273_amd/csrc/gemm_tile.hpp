@@ -30,6 +30,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace g355 {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -89,21 +92,33 @@ struct GemmArgs {
   void *C; int64_t ldc;
 };
 
-// Tile shape: BM x BN outputs per workgroup, WM x WN waves (64 lanes each).
-template <int BM_, int BN_, int WM_, int WN_> struct Shape {
-  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
-  static constexpr int NT = 64 * WM * WN;
+// Tile shape: BM x BN outputs per workgroup, WM x WN wave positions (64
+// lanes each), KS waves per position splitting every K-tile between them
+// (their partial sums are added through LDS at the end of the tile).
+template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1> struct Shape {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KS = KS_;
+  static constexpr int NT = 64 * WM * WN * KS;
   static constexpr int WTM = BM / WM, WTN = BN / WN;   // per-wave tile
   static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 blocks per wave
   static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "bad shape");
 };
+
+// A K split needs every wave's share of a K-tile to hold whole MFMA steps.
+template <int P, class S> __host__ __device__ constexpr bool shape_ok() {
+  constexpr int KG = Traits<P>::BK / 4;
+  return KG % S::KS == 0 && (KG / S::KS) % Traits<P>::KPL == 0;
+}
 
 template <int P> __host__ __device__ constexpr int lds_pad() {
   return 16 / (int)sizeof(typename Traits<P>::E);       // 16 bytes per row
 }
 template <int P, class S> __host__ __device__ constexpr int lds_bytes() {
   using T = Traits<P>;
-  return 2 * T::PLANES * (S::BM + S::BN) * (T::BK + lds_pad<P>()) * (int)sizeof(typename T::E);
+  constexpr int stages =
+      2 * T::PLANES * (S::BM + S::BN) * (T::BK + lds_pad<P>()) * (int)sizeof(typename T::E);
+  // K-split reduction: one wave column (BM x WTN accumulators) at a time
+  constexpr int red = S::KS > 1 ? S::BM * S::WTN * (int)sizeof(typename T::Acc) / 4 : 0;
+  return stages > red ? stages : red;
 }
 
 // Buffer resource over `base` for raw buffer loads (CDNA: 32-bit data
@@ -203,6 +218,15 @@ struct Mover {
 
 // Compute one BM x BN tile of C at (m0, n0). TA: op(A) = A^T (A stored
 // K x M); TB: op(B) = B^T (B stored N x K). VEC: 16-byte loads allowed.
+//
+// Schedule of one K-tile for one wave (U read units of the wave's K range):
+//   issue global loads of K-tile t+1 into VGPRs
+//   for each unit u < U-1: LDS reads of unit u+1 | MFMAs of unit u
+//   MFMAs of the first half of the last unit's blocks
+//   VGPRs -> LDS stage of t+1; barrier; LDS reads of unit 0 of t+1
+//   MFMAs of the second half of the last unit's blocks
+// so the global-load latency is covered by the MFMAs before the store, and
+// the barrier and the first LDS reads of the next tile by the last half.
 template <int P, class S, bool TA, bool TB, bool VEC>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t n0,
                                           char *smem) {
@@ -211,17 +235,24 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
   using Op = typename T::Op;
   using Acc = typename T::Acc;
   using Out = typename T::Out;
-  constexpr int BK = T::BK, KPL = T::KPL, PL = T::PLANES;
+  constexpr int BK = T::BK, KPL = T::KPL, PL = T::PLANES, KS = S::KS;
   constexpr int LDW = BK + lds_pad<P>();
-  constexpr int KG = BK / 4;            // K elements per lane group per tile
-  constexpr int STEPS = KG / KPL;       // MFMA steps per K-tile
+  constexpr int KG = BK / 4;             // K elements per lane group per tile
+  constexpr int KW = KG / KS;            // ... owned by one wave of a K split
+  constexpr int RU = (16 / (int)sizeof(E)) < KW ? (16 / (int)sizeof(E)) : KW;  // per read
+  constexpr int U = KW / RU;             // read units per tile per wave
+  constexpr int SPU = RU / KPL;          // MFMA steps per read unit
+  static_assert(KG % KS == 0 && KW % RU == 0 && RU % KPL == 0, "bad K split");
   constexpr int NT = S::NT;
   constexpr int A_ELEMS = S::BM * LDW, B_ELEMS = S::BN * LDW;
   constexpr int STAGE = PL * (A_ELEMS + B_ELEMS);
+  constexpr int NB = S::FM * S::FN;      // 16x16 blocks per wave
+  constexpr int NB1 = NB / 2;            // blocks before the barrier in the last unit
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave % S::WM, wn = wave / S::WM;
+  const int wpos = wave % (S::WM * S::WN), kh = wave / (S::WM * S::WN);
+  const int wm = wpos % S::WM, wn = wpos / S::WM;
   const int lr = lane & 15, lgp = lane >> 4;
 
   E *lds = reinterpret_cast<E *>(smem);
@@ -263,56 +294,120 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
     }
   };
 
-  if (KT > 0) {
-    load_tile(0);
-    store_tile(0);
-  }
-  __syncthreads();
-
-  for (int64_t kt = 0; kt < KT; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < KT) load_tile(kt + 1);
-
-    const E *st = lds + cur * STAGE;
-    Op fa[PL][S::FM][STEPS], fb[PL][S::FN][STEPS];
+  // Fragments of one read unit: RU consecutive K elements per lane for each
+  // block row (A) and block column (B); double-buffered across units.
+  using Unit = VecT<E, RU>;
+  Unit fa[2][PL][S::FM], fb[2][PL][S::FN];
+  auto read_unit = [&](int stage, int u, auto buf_tag) {
+    constexpr int b = decltype(buf_tag)::value;
+    const E *st = lds + stage * STAGE;
+    const int koff = lgp * KG + kh * KW + u * RU;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
 #pragma unroll
-      for (int i = 0; i < S::FM; ++i) {
-        const Op *src = reinterpret_cast<const Op *>(
-            st + pl * A_ELEMS + (wm * S::WTM + i * 16 + lr) * LDW + lgp * KG);
+      for (int i = 0; i < S::FM; ++i)
+        fa[b][pl][i] = *reinterpret_cast<const Unit *>(
+            st + pl * A_ELEMS + (wm * S::WTM + i * 16 + lr) * LDW + koff);
 #pragma unroll
-        for (int s = 0; s < STEPS; ++s) fa[pl][i][s] = src[s];
-      }
-#pragma unroll
-      for (int j = 0; j < S::FN; ++j) {
-        const Op *src = reinterpret_cast<const Op *>(
-            st + PL * A_ELEMS + pl * B_ELEMS + (wn * S::WTN + j * 16 + lr) * LDW + lgp * KG);
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) fb[pl][j][s] = src[s];
-      }
+      for (int j = 0; j < S::FN; ++j)
+        fb[b][pl][j] = *reinterpret_cast<const Unit *>(
+            st + PL * A_ELEMS + pl * B_ELEMS + (wn * S::WTN + j * 16 + lr) * LDW + koff);
     }
+  };
+  auto op_of = [](const Unit &u, int step) {
+    return *reinterpret_cast<const Op *>(&u.e[step * KPL]);
+  };
+  // MFMAs of blocks [lo, hi) of a unit, every step of the unit.
+  auto mma_unit = [&](auto buf_tag, auto lo_tag, auto hi_tag) {
+    constexpr int b = decltype(buf_tag)::value;
+    constexpr int lo = decltype(lo_tag)::value, hi = decltype(hi_tag)::value;
 #pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
+    for (int st = 0; st < SPU; ++st) {
       if constexpr (PL == 2) {
         // small cross terms first, then hi*hi, into one accumulator
 #pragma unroll
-        for (int i = 0; i < S::FM; ++i)
+        for (int x = lo; x < hi; ++x)
+          mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][1][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
 #pragma unroll
-          for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[1][i][s], fb[0][j][s]);
-#pragma unroll
-        for (int i = 0; i < S::FM; ++i)
-#pragma unroll
-          for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[0][i][s], fb[1][j][s]);
+        for (int x = lo; x < hi; ++x)
+          mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][1][x % S::FN], st));
       }
 #pragma unroll
-      for (int i = 0; i < S::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < S::FN; ++j) mfma(acc[i][j], fa[0][i][s], fb[0][j][s]);
+      for (int x = lo; x < hi; ++x)
+        mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
     }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using INB1 = std::integral_constant<int, NB1>;
+  using INB = std::integral_constant<int, NB>;
 
-    if (kt + 1 < KT) store_tile(cur ^ 1);
+  // One K-tile; P0 is the fragment buffer of its unit 0 (static, so the
+  // fragments stay in registers; with an odd U the parity alternates and the
+  // loop below is unrolled by two).
+  auto ktile = [&](auto p0_tag, int64_t kt) {
+    constexpr int P0 = decltype(p0_tag)::value;
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < KT;
+    if (more) load_tile(kt + 1);
+    [&]<int... u>(std::integer_sequence<int, u...>) {
+      ((read_unit(cur, u + 1, std::integral_constant<int, (P0 + u + 1) & 1>{}),
+        mma_unit(std::integral_constant<int, (P0 + u) & 1>{}, I0{}, INB{})), ...);
+    }(std::make_integer_sequence<int, U - 1>{});
+    constexpr int PL_ = (P0 + U - 1) & 1;
+    mma_unit(std::integral_constant<int, PL_>{}, I0{}, INB1{});
+    if (more) store_tile(cur ^ 1);
     __syncthreads();
+    if (more) read_unit(cur ^ 1, 0, std::integral_constant<int, (P0 + U) & 1>{});
+    mma_unit(std::integral_constant<int, PL_>{}, INB1{}, INB{});
+  };
+
+  if (KT > 0) {
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+    read_unit(0, 0, I0{});
+    if constexpr (U % 2 == 0) {
+      for (int64_t kt = 0; kt < KT; ++kt) ktile(I0{}, kt);
+    } else {
+      for (int64_t kt = 0; kt < KT; kt += 2) {
+        ktile(I0{}, kt);
+        if (kt + 1 < KT) ktile(std::integral_constant<int, 1>{}, kt + 1);
+      }
+    }
+  }
+
+  // K split: waves kh > 0 hand their partial sums to kh = 0 through LDS, one
+  // wave column at a time (the operand stages are free after the last barrier).
+  if constexpr (KS > 1) {
+    using AE = std::remove_reference_t<decltype(acc[0][0][0])>;
+    AE *red = reinterpret_cast<AE *>(smem);
+#pragma unroll 1
+    for (int col = 0; col < S::WN; ++col) {
+#pragma unroll 1
+      for (int h = 1; h < KS; ++h) {
+        if (wn == col && kh == h) {
+#pragma unroll
+          for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane] = acc[i][j][q];
+        }
+        __syncthreads();
+        if (wn == col && kh == 0) {
+#pragma unroll
+          for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                acc[i][j][q] += red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane];
+        }
+        __syncthreads();
+      }
+    }
+    if (kh != 0) return;
   }
 
   // Epilogue: lane holds column lane%16 of each 16x16 block and the four

@@ -1,0 +1,416 @@
+// gemm_tile_dma.hpp -- the tile routine with direct-to-LDS operand loads.
+//
+// Same product and MFMA mapping as gemm_tile (Hasta and Mutiara, Section 3.1,
+// Algorithm 1, reduction blocked over K-tiles), different data movement:
+// operands go HBM/L2 -> LDS with `buffer_load_dwordx4 ... lds` (no VGPR
+// staging), into a ring of three LDS stages, two K-tiles ahead of the
+// MFMAs. Waits are explicit: every wave issues the same number of 16-byte
+// transfers per K-tile, so `s_waitcnt vmcnt(n)` with n = one tile's count
+// retires exactly the tile about to be read; a barrier then makes all
+// waves' transfers visible.
+//
+// LDS layouts (one transfer instruction fills 1 KiB: lane l -> base + 16 l):
+//  * K-contiguous operand (A not transposed, B transposed): rows of BK
+//    elements, 16-byte chunks XOR-swizzled per row (chunk c of row r holds
+//    global chunk c ^ swz(r)) so that sixteen lanes reading the same K
+//    offset of sixteen rows hit distinct banks.
+//  * MN-contiguous operand (A transposed, B not transposed), 4- and 8-byte
+//    elements only: rows of R elements, one per k, as in memory; a lane's
+//    MFMA operand is one element, read per step from row k.
+#pragma once
+
+#include "gemm_tile.hpp"
+
+namespace g355 {
+
+#define G355_LDS(p) ((__attribute__((address_space(3))) void *)(p))
+
+// s_waitcnt encodings (gfx9): vmcnt in bits [3:0] and [15:14], expcnt [6:4],
+// lgkmcnt [11:8]; unused counters at their maximum.
+template <int VM> __device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(VM >= 0 && VM < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((VM & 0xF) | ((VM >> 4) << 14) | (0x7 << 4) | (0x0 << 8));
+}
+// One 16-byte-per-lane transfer HBM/L2 -> LDS: lane l's 16 bytes at buffer
+// offset `voff` land at LDS byte address lds_base + 16 l (an offset at or
+// above the buffer's record count reads as zeros). Issued from inline
+// assembly so that the compiler does not add a wait for all outstanding
+// transfers before every later LDS read (it cannot tell the ring stages
+// apart); the kernel retires transfers itself with wait_vm_lgkm0. The
+// instruction writes no VGPR; VMEM loads retire in order, so transfers the
+// compiler does not know about only make its own vmcnt waits stricter.
+typedef unsigned int srd_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ srd_t make_srd(const void *base) {
+  const uint64_t a = (uint64_t)(uintptr_t)base;
+  srd_t r;
+  r.x = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  r.y = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32) & 0xFFFFu);
+  r.z = 0x7fffffffu;      // record count (bytes)
+  r.w = 0x00020000u;      // 32-bit data format (CDNA)
+  return r;
+}
+__device__ __forceinline__ void lds_dma16(srd_t srd, uint32_t voff, uint32_t lds_base) {
+  asm volatile(
+      "s_mov_b32 m0, %2\n\t"
+      "s_nop 0\n\t"
+      "buffer_load_dwordx4 %0, %1, 0 offen lds"
+      :
+      : "v"(voff), "s"(srd), "s"(lds_base)
+      : "memory", "m0");
+}
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+}
+
+// Workgroup barrier without the memory fence of __syncthreads (whose release
+// would wait for every outstanding LDS transfer); the signal fences keep the
+// compiler from moving memory operations across it.
+__device__ __forceinline__ void raw_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// One operand plane of one K-tile: R rows (M or N) x BK.
+template <typename E, int R, int BK, int NT, bool KC>
+struct DmaOp {
+  static constexpr int ES = (int)sizeof(E);
+  static constexpr int V = 16 / ES;                  // elements per chunk
+  static constexpr int RB = KC ? BK * ES : R * ES;   // bytes per LDS row
+  static constexpr int NROWS = KC ? R : BK;
+  static constexpr int CPR = RB / 16;                // chunks per row
+  static constexpr int CHUNKS = NROWS * CPR;
+  static constexpr int NI = CHUNKS / 64;             // transfers per tile
+  static constexpr int NW = NT / 64;
+  static constexpr int PERW = NI / NW;               // transfers per wave per tile
+  static constexpr int BYTES = CHUNKS * 16;
+  static constexpr bool OK = (RB % 16 == 0) && (CHUNKS % 64 == 0) && (NI % NW == 0) &&
+                             (PERW >= 1) && (KC || ES >= 4) && (!KC || RB <= 256);
+
+  uint32_t off[PERW > 0 ? PERW : 1];
+  int32_t kk[PERW > 0 ? PERW : 1];   // K index of the chunk (first element)
+  bool rok[PERW > 0 ? PERW : 1];     // M/N index inside the matrix
+
+  __device__ __forceinline__ static int swz(int r) { return ((r * RB) >> 8) % CPR; }
+
+  __device__ __forceinline__ void init(int64_t ld, int64_t r0, int64_t rtot, int wave, int lane) {
+#pragma unroll
+    for (int j = 0; j < PERW; ++j) {
+      const int q = (wave + j * NW) * 64 + lane;
+      const int r = q / CPR, c = q % CPR;
+      if constexpr (KC) {
+        const int k = (c ^ swz(r)) * V;
+        off[j] = (uint32_t)(((int64_t)r * ld + k) * ES);
+        kk[j] = k;
+        rok[j] = r0 + r < rtot;
+      } else {
+        const int m = c * V;
+        off[j] = (uint32_t)(((int64_t)r * ld + m) * ES);
+        kk[j] = r;
+        rok[j] = r0 + m < rtot;
+      }
+    }
+  }
+
+  // tile_base: element (r0, k0) for KC, (k0, r0) otherwise.
+  __device__ __forceinline__ void issue(const E *tile_base, int64_t k0, int64_t K, char *region,
+                                        int wave) const {
+    const srd_t srd = make_srd(tile_base);
+    const uint32_t base = lds_addr(region);
+#pragma unroll
+    for (int j = 0; j < PERW; ++j) {
+      const bool ok = rok[j] && (k0 + kk[j] < K);
+      const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave + j * NW) * 1024u);
+      lds_dma16(srd, ok ? off[j] : kOob, dst);
+    }
+  }
+
+  // Transfer j of this wave for the K-tile at tile_base (see issue()).
+  __device__ __forceinline__ void issue_one(int j, const srd_t &srd, int64_t k0, int64_t K,
+                                            uint32_t base, int wave) const {
+    const bool ok = rok[j] && (k0 + kk[j] < K);
+    const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave + j * NW) * 1024u);
+    __builtin_amdgcn_sched_barrier(0);
+    lds_dma16(srd, ok ? off[j] : kOob, dst);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // RU consecutive K elements (K offset koff, a multiple of RU) of LDS row
+  // `row` (KC) or column `row` (MN).
+  template <int RU>
+  __device__ __forceinline__ static VecT<E, RU> read(const char *region, int row, int koff) {
+    VecT<E, RU> v;
+    if constexpr (KC) {
+      const int c = koff / V, e0 = koff % V;
+      v = *reinterpret_cast<const VecT<E, RU> *>(region + row * RB + ((c ^ swz(row)) * 16) + e0 * ES);
+    } else {
+#pragma unroll
+      for (int e = 0; e < RU; ++e)
+        v.e[e] = *reinterpret_cast<const E *>(region + (koff + e) * RB + row * ES);
+    }
+    return v;
+  }
+};
+
+template <int P, class S, bool TA, bool TB> struct DmaPlan {
+  using T = Traits<P>;
+  using E = typename T::E;
+  using OA = DmaOp<E, S::BM, T::BK, S::NT, !TA>;
+  using OB = DmaOp<E, S::BN, T::BK, S::NT, TB>;
+  static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
+  static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
+  static constexpr bool OK = OA::OK && OB::OK && shape_ok<P, S>() && PER_WAVE < 32 &&
+                             (TA ? T::KPL == 1 : true) && (TB ? true : T::KPL == 1);
+};
+
+template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr bool dma_ok() {
+  return DmaPlan<P, S, TA, TB>::OK;
+}
+
+template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr int lds_bytes_dma() {
+  using T = Traits<P>;
+  constexpr int stages = 3 * DmaPlan<P, S, TA, TB>::STAGE;
+  constexpr int red = S::KS > 1 ? S::BM * S::WTN * (int)sizeof(typename T::Acc) / 4 : 0;
+  return stages > red ? stages : red;
+}
+
+// Compute one BM x BN tile of C at (m0, n0) with direct-to-LDS operands.
+// Same contract as gemm_tile with VEC = true.
+template <int P, class S, bool TA, bool TB>
+__device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int64_t n0,
+                                              char *smem) {
+  using T = Traits<P>;
+  using E = typename T::E;
+  using Op = typename T::Op;
+  using Acc = typename T::Acc;
+  using Out = typename T::Out;
+  using Plan = DmaPlan<P, S, TA, TB>;
+  using OA = typename Plan::OA;
+  using OB = typename Plan::OB;
+  static_assert(Plan::OK, "shape/layout not offered on the direct-to-LDS path");
+  constexpr int BK = T::BK, KPL = T::KPL, PL = T::PLANES, KS = S::KS;
+  constexpr int KG = BK / 4, KW = KG / KS;
+  constexpr int VE = 16 / (int)sizeof(E);
+  constexpr int RU = VE < KW ? VE : KW;
+  constexpr int U = KW / RU, SPU = RU / KPL;
+  constexpr int NB = S::FM * S::FN, NB1 = NB / 2;
+  constexpr int STAGE = Plan::STAGE, DPW = Plan::PER_WAVE;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wpos = wave % (S::WM * S::WN), kh = wave / (S::WM * S::WN);
+  const int wm = wpos % S::WM, wn = wpos / S::WM;
+  const int lr = lane & 15, lgp = lane >> 4;
+
+  const E *Ap[2] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2)};
+  const E *Bp[2] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2)};
+  OA oa;
+  OB ob;
+  oa.init(g.lda, m0, g.M, wave, lane);
+  ob.init(g.ldb, n0, g.N, wave, lane);
+
+  // region of plane pl of operand A / B in stage st
+  auto regA = [&](int st, int pl) { return smem + st * STAGE + pl * OA::BYTES; };
+  auto regB = [&](int st, int pl) { return smem + st * STAGE + PL * OA::BYTES + pl * OB::BYTES; };
+
+  const int64_t KT = (g.K + BK - 1) / BK;
+  auto issue_tile = [&](int64_t kt) {
+    const int st = (int)(kt % 3);
+    const int64_t k0 = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+      const E *ta = TA ? Ap[pl] + k0 * g.lda + m0 : Ap[pl] + m0 * g.lda + k0;
+      const E *tb = TB ? Bp[pl] + n0 * g.ldb + k0 : Bp[pl] + k0 * g.ldb + n0;
+      oa.issue(ta, k0, g.K, regA(st, pl), wave);
+      ob.issue(tb, k0, g.K, regB(st, pl), wave);
+    }
+  };
+
+  Acc acc[S::FM][S::FN];
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
+
+  using Unit = VecT<E, RU>;
+  Unit fa[2][PL][S::FM], fb[2][PL][S::FN];
+  auto read_unit = [&](int st, int u, auto buf_tag) {
+    constexpr int b = decltype(buf_tag)::value;
+    const int koff = lgp * KG + kh * KW + u * RU;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i)
+        fa[b][pl][i] = OA::template read<RU>(regA(st, pl), wm * S::WTM + i * 16 + lr, koff);
+#pragma unroll
+      for (int j = 0; j < S::FN; ++j)
+        fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * 16 + lr, koff);
+    }
+  };
+  auto op_of = [](const Unit &u, int step) {
+    return *reinterpret_cast<const Op *>(&u.e[step * KPL]);
+  };
+
+  // Transfers of the K-tile two ahead are spread over the MFMAs issued
+  // before the barrier: a 1 KiB transfer occupies the CU's address unit for
+  // many cycles, and a wave queued behind it issues no MFMA meanwhile.
+  // Transfer k goes right before pre-barrier MFMA number k * NPRE / DPW.
+  constexpr int MPB = SPU * (PL == 2 ? 3 : 1);          // MFMAs per block per unit
+  constexpr int NPRE = MPB * ((U - 1) * NB + NB1);       // pre-barrier MFMAs per tile
+  struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; bool on; };
+  Pending pend;
+  auto prep_tile = [&](int64_t kt) {
+    pend.on = kt < KT;
+    if (!pend.on) return;
+    const int st = (int)(kt % 3);
+    pend.k0 = kt * BK;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl) {
+      const E *ta = TA ? Ap[pl] + pend.k0 * g.lda + m0 : Ap[pl] + m0 * g.lda + pend.k0;
+      const E *tb = TB ? Bp[pl] + n0 * g.ldb + pend.k0 : Bp[pl] + pend.k0 * g.ldb + n0;
+      pend.sa[pl] = make_srd(ta);
+      pend.sb[pl] = make_srd(tb);
+      pend.la[pl] = lds_addr(regA(st, pl));
+      pend.lb[pl] = lds_addr(regB(st, pl));
+    }
+  };
+  auto issue_k = [&](auto k_tag) {   // transfer k of the pending tile
+    constexpr int k = decltype(k_tag)::value;
+    constexpr int per_plane = OA::PERW + OB::PERW;
+    constexpr int pl = k / per_plane, r = k % per_plane;
+    if (pend.on) {
+      if constexpr (r < OA::PERW)
+        oa.issue_one(r, pend.sa[pl], pend.k0, g.K, pend.la[pl], wave);
+      else
+        ob.issue_one(r - OA::PERW, pend.sb[pl], pend.k0, g.K, pend.lb[pl], wave);
+    }
+  };
+  // pre-barrier MFMA number n: issue every transfer k with k * NPRE / DPW == n
+  auto maybe_issue = [&](auto n_tag) {
+    constexpr int n = decltype(n_tag)::value;
+    [&]<int... k>(std::integer_sequence<int, k...>) {
+      ((void)((k * NPRE / DPW == n) ? (issue_k(std::integral_constant<int, k>{}), 0) : 0), ...);
+    }(std::make_integer_sequence<int, DPW>{});
+  };
+  // MFMAs of blocks [lo, hi) of a unit; SLOT is the pre-barrier number of the
+  // first one (or -1 after the barrier: no transfers there).
+  auto mma_unit_s = [&](auto buf_tag, auto lo_tag, auto hi_tag, auto slot_tag) {
+    constexpr int b = decltype(buf_tag)::value;
+    constexpr int lo = decltype(lo_tag)::value, hi = decltype(hi_tag)::value;
+    constexpr int SLOT = decltype(slot_tag)::value;
+    constexpr int NX = hi - lo;
+    [&]<int... m>(std::integer_sequence<int, m...>) {
+      (([&] {
+         constexpr int st = m / ((PL == 2 ? 3 : 1) * NX);
+         constexpr int term = (m / NX) % (PL == 2 ? 3 : 1);   // 0: lo*hi, 1: hi*lo, 2: hi*hi
+         constexpr int x = lo + m % NX;
+         if constexpr (SLOT >= 0) maybe_issue(std::integral_constant<int, SLOT + m>{});
+         if constexpr (PL == 2 && term == 0)
+           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][1][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
+         else if constexpr (PL == 2 && term == 1)
+           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][1][x % S::FN], st));
+         else
+           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
+       }()), ...);
+    }(std::make_integer_sequence<int, SPU * (PL == 2 ? 3 : 1) * NX>{});
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using INB1 = std::integral_constant<int, NB1>;
+  using INB = std::integral_constant<int, NB>;
+
+  // One K-tile: issue the transfers two tiles ahead, MFMAs on this tile,
+  // retire the next tile's transfers, barrier, first fragments of the next
+  // tile under the last half of this tile's MFMAs.
+  auto ktile = [&](auto p0_tag, int64_t kt) {
+    constexpr int P0 = decltype(p0_tag)::value;
+    const int cur = (int)(kt % 3);
+    prep_tile(kt + 2);
+    [&]<int... u>(std::integer_sequence<int, u...>) {
+      ((read_unit(cur, u + 1, std::integral_constant<int, (P0 + u + 1) & 1>{}),
+        mma_unit_s(std::integral_constant<int, (P0 + u) & 1>{}, I0{}, INB{},
+                   std::integral_constant<int, u * MPB * NB>{})), ...);
+    }(std::make_integer_sequence<int, U - 1>{});
+    constexpr int PLU = (P0 + U - 1) & 1;
+    mma_unit_s(std::integral_constant<int, PLU>{}, I0{}, INB1{},
+               std::integral_constant<int, (U - 1) * MPB * NB>{});
+    if (kt + 1 < KT) {
+      if (kt + 2 < KT) wait_vm_lgkm0<DPW>();   // tile kt+2 may stay in flight
+      else wait_vm_lgkm0<0>();
+      raw_barrier();
+      read_unit((int)((kt + 1) % 3), 0, std::integral_constant<int, (P0 + U) & 1>{});
+    }
+    mma_unit_s(std::integral_constant<int, PLU>{}, INB1{}, INB{}, std::integral_constant<int, -1>{});
+  };
+
+  if (KT > 0) {
+    issue_tile(0);
+    if (KT > 1) {
+      issue_tile(1);
+      wait_vm_lgkm0<DPW>();
+    } else {
+      wait_vm_lgkm0<0>();
+    }
+    raw_barrier();
+    read_unit(0, 0, I0{});
+    if constexpr (U % 2 == 0) {
+      for (int64_t kt = 0; kt < KT; ++kt) ktile(I0{}, kt);
+    } else {
+      for (int64_t kt = 0; kt < KT; kt += 2) {
+        ktile(I0{}, kt);
+        if (kt + 1 < KT) ktile(std::integral_constant<int, 1>{}, kt + 1);
+      }
+    }
+    // every wave has finished its LDS reads before the stages are reused
+    wait_vm_lgkm0<0>();
+    raw_barrier();
+  }
+
+  if constexpr (KS > 1) {
+    using AE = std::remove_reference_t<decltype(acc[0][0][0])>;
+    AE *red = reinterpret_cast<AE *>(smem);
+#pragma unroll 1
+    for (int col = 0; col < S::WN; ++col) {
+#pragma unroll 1
+      for (int h = 1; h < KS; ++h) {
+        if (wn == col && kh == h) {
+#pragma unroll
+          for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane] = acc[i][j][q];
+        }
+        __syncthreads();
+        if (wn == col && kh == 0) {
+#pragma unroll
+          for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                acc[i][j][q] += red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane];
+        }
+        __syncthreads();
+      }
+    }
+    if (kh != 0) return;
+  }
+
+  constexpr int GRP = T::GRP;
+  Out *C = reinterpret_cast<Out *>(g.C);
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i) {
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) {
+      const int64_t col = n0 + wn * S::WTN + j * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = m0 + wm * S::WTM + i * 16 + (q / GRP) * 4 * GRP + lgp * GRP + q % GRP;
+        if (row < g.M && col < g.N) C[row * g.ldc + col] = (Out)acc[i][j][q];
+      }
+    }
+  }
+}
+
+}  // namespace g355

@@ -18,10 +18,11 @@ struct GemmArgs;
 // persistent grouped kernel; the others run as single-product launches.
 enum TileCfg : int {
   CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3, CFG_GROUPED_COUNT = 4,
-  CFG_128x128_W8 = 4, CFG_COUNT = 5
+  CFG_128x128_W8 = 4, CFG_128x128_K2 = 5, CFG_128x64_K2 = 6, CFG_COUNT = 7
 };
 struct CfgInfo { int bm, bn; const char *name; };
 const CfgInfo &cfg_info(int id);
+bool cfg_supported(int prec, int cfg);
 
 // Operand layout of one launch: TA -> op(A) = A^T stored K x M;
 // TB -> op(B) = B^T stored N x K.
