@@ -31,7 +31,8 @@ void clear_error() { t_err.clear(); }
 static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x64"},
                                          {64, 64, "64x64"},     {32, 32, "32x32"},
                                          {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
-                                         {128, 64, "128x64k2"}};
+                                         {128, 64, "128x64k2"},   {64, 64, "64x64k2"},
+                                         {32, 32, "32x32k2"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
@@ -40,8 +41,13 @@ static std::atomic<int> g_force_cfg{-1};
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
-  if (cfg == CFG_128x128_K2 || cfg == CFG_128x64_K2) return prec == PREC_F64 || prec == PREC_F32;
+  if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   return true;
+}
+bool cfg_grouped(int cfg) {
+  for (int c : kGroupedCfgs)
+    if (c == cfg) return true;
+  return false;
 }
 
 static int device_cus() {
@@ -60,27 +66,34 @@ static int device_cus() {
   return cus;
 }
 
-// Tile shape for one product: minimise (tiles per CU, rounded up) x tile
-// area / relative efficiency of the shape. Larger tiles re-read less of A
-// and B per flop and keep more independent MFMAs in flight; smaller ones
-// fill the 256 CUs when C is small.
+// Tile shape for one product, from measured sweeps on MI355X (square
+// products N = 500 .. 8192, every shape forced in turn). The deciding
+// quantity is how many 128 x 128 tiles C has against the 256 CUs: with
+// fewer than ~48 smaller tiles are needed to occupy the CUs, up to ~200 the
+// medium shapes win, above that the two-waves-per-SIMD shapes (K split for
+// binary64, 8 waves for the split product) or the 128 x 64 shape (bf16,
+// whose 16-bit MFMAs need more resident waves to hide LDS latency).
 static int choose_cfg(int prec, int64_t m, int64_t n) {
   const int forced = g_force_cfg.load();
   if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced)) return forced;
-  static const double eff_f64[CFG_COUNT] = {1.0, 0.95, 0.85, 0.6, 0.98, 0.99, 0.9};
-  static const double eff_lp[CFG_COUNT] = {1.0, 0.85, 0.65, 0.35, 0.98, 0.99, 0.85};
-  const double *eff = (prec == PREC_F64) ? eff_f64 : eff_lp;
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
   const int64_t cus = device_cus();
-  int best = CFG_128x128;
-  double best_cost = 0;
-  for (int c = 0; c < CFG_COUNT; ++c) {
-    if (!cfg_supported(prec, c)) continue;
-    const int64_t tiles = ((m + kCfgs[c].bm - 1) / kCfgs[c].bm) * ((n + kCfgs[c].bn - 1) / kCfgs[c].bn);
-    const int64_t waves = (tiles + cus - 1) / cus;
-    const double cost = (double)waves * kCfgs[c].bm * kCfgs[c].bn / eff[c];
-    if (c == 0 || cost < best_cost) { best = c; best_cost = cost; }
+  const int64_t big = cus * 200 / 256, mid = cus * 48 / 256;
+  switch (prec) {
+    case PREC_F64:
+      if (t128 >= big) return CFG_128x128_K2;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+    case PREC_F32:
+      if (t128 >= 2 * cus) return CFG_128x128;
+      if (t128 >= big) return CFG_128x64_K2;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+    case PREC_BF16:
+      if (t128 >= big) return CFG_128x64;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+    default:  // split
+      if (t128 >= big) return CFG_128x128_W8;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
   }
-  return best;
 }
 
 static size_t esize_of(int dtype) {
@@ -260,8 +273,7 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
     // planes carry zeros in the padding columns [k, kp), so the product may
     // run over kp (a whole number of 8-element vectors) unchanged
     if ((rc = check_ld_range("A", lda, 4)) || (rc = check_ld_range("B", ldb, 4))) return rc;
-    hipError_t e = launch_split(m, k, A, lda, false, ahi, alo, kp, kp, s);
-    if (e == hipSuccess) e = launch_split(k, n, B, ldb, true, bhi, blo, kp, kp, s);
+    hipError_t e = launch_split_pair(m, n, k, A, lda, B, ldb, ahi, alo, bhi, blo, kp, s);
     if (e != hipSuccess) return hip_fail(e, "split launch");
   }
   GemmArgs a{m, n, k > 0 ? kp : 0, ahi, kp, bhi, kp, alo, blo, C, ldc};

@@ -47,7 +47,7 @@ enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3 };
 //   Op   the per-lane operand of one MFMA
 //   Acc  the per-lane accumulator of one 16x16 output block
 //   KPL  K elements per lane per MFMA (16x16x4 -> 1, 16x16x32 -> 8)
-//   BK   K-tile depth
+//   BK   K-tile depth of the small shapes (see bk_of)
 //   GRP  rows per lane group in the 16x16 output block: lane l holds column
 //        l%16 and rows (q/GRP)*4*GRP + (l/16)*GRP + q%GRP, q = 0..3
 //        (binary64: rows 4q + l/16; binary32 accumulators: rows 4(l/16) + q)
@@ -66,7 +66,7 @@ template <> struct Traits<PREC_BF16> {
 };
 template <> struct Traits<PREC_SPLIT> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 32, PLANES = 2, GRP = 4;   // hi and lo planes
+  static constexpr int KPL = 8, BK = 64, PLANES = 2, GRP = 4;   // hi and lo planes
 };
 
 __device__ __forceinline__ void mfma(f64x4 &acc, double a, double b) {
@@ -77,6 +77,12 @@ __device__ __forceinline__ void mfma(f32x4 &acc, float a, float b) {
 }
 __device__ __forceinline__ void mfma(f32x4 &acc, u16x8 a, u16x8 b) {
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ void mfma(f32x16 &acc, u16x8 a, u16x8 b) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
 }
 
@@ -102,6 +108,15 @@ template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1> struct Shape {
   static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 blocks per wave
   static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "bad shape");
 };
+
+// K-tile depth of a (precision, shape) pair on the direct-to-LDS path:
+// binary64 tiles of 128 x 128 outputs and more take 32-deep K-tiles (twice
+// the MFMA work per barrier); smaller ones keep 16 so that several
+// workgroups fit in LDS. The register path uses Traits<P>::BK throughout.
+template <int P, class S> __host__ __device__ constexpr int bk_of() {
+  if constexpr (P == PREC_F64) return S::BM * S::BN >= 128 * 128 ? 32 : 16;
+  else return Traits<P>::BK;
+}
 
 // A K split needs every wave's share of a K-tile to hold whole MFMA steps.
 template <int P, class S> __host__ __device__ constexpr bool shape_ok() {

@@ -152,14 +152,35 @@ struct DmaOp {
   }
 };
 
+// MFMA block geometry on this path: the 16-bit precisions use 32 x 32 x 16
+// blocks (two lane groups of 32, sixteen binary32 accumulators per lane)
+// when the wave tile is a multiple of 32 both ways, else 16 x 16 blocks.
+//   lane l: block row/column l % MB, lane group l / MB; output register v
+//   of lane group g holds row (v / GRP) * (LGN * GRP) + g * GRP + v % GRP.
+template <int P, class S> struct Geom {
+  static constexpr bool BIG = Traits<P>::KPL == 8 && S::WTM % 32 == 0 && S::WTN % 32 == 0;
+  static constexpr int MB = BIG ? 32 : 16;
+  static constexpr int LGN = 64 / MB;
+  static constexpr int NR = MB * MB / 64;
+  static constexpr int FM = S::WTM / MB, FN = S::WTN / MB;
+  static constexpr int KG = bk_of<P, S>() / LGN;    // K elements per lane group per tile
+  using Acc = typename std::conditional<BIG, f32x16, typename Traits<P>::Acc>::type;
+  static constexpr bool OK = KG % S::KS == 0 && (KG / S::KS) % Traits<P>::KPL == 0 &&
+                             FM >= 1 && FN >= 1;
+};
+
 template <int P, class S, bool TA, bool TB> struct DmaPlan {
   using T = Traits<P>;
   using E = typename T::E;
-  using OA = DmaOp<E, S::BM, T::BK, S::NT, !TA>;
-  using OB = DmaOp<E, S::BN, T::BK, S::NT, TB>;
+  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA>;
+  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB>;
   static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
+  // ring depth: three stages (transfers two K-tiles ahead) when they fit in
+  // 144 KiB of the 160 KiB LDS, else two (one tile ahead)
+  static constexpr int NS = 3 * STAGE <= 144 * 1024 ? 3 : 2;
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
-  static constexpr bool OK = OA::OK && OB::OK && shape_ok<P, S>() && PER_WAVE < 32 &&
+  static constexpr bool OK = OA::OK && OB::OK && Geom<P, S>::OK && PER_WAVE < 32 &&
+                             NS * STAGE <= 160 * 1024 &&
                              (TA ? T::KPL == 1 : true) && (TB ? true : T::KPL == 1);
 };
 
@@ -169,7 +190,7 @@ template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr bool d
 
 template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr int lds_bytes_dma() {
   using T = Traits<P>;
-  constexpr int stages = 3 * DmaPlan<P, S, TA, TB>::STAGE;
+  constexpr int stages = DmaPlan<P, S, TA, TB>::NS * DmaPlan<P, S, TA, TB>::STAGE;
   constexpr int red = S::KS > 1 ? S::BM * S::WTN * (int)sizeof(typename T::Acc) / 4 : 0;
   return stages > red ? stages : red;
 }
@@ -180,27 +201,30 @@ template <int P, class S, bool TA, bool TB>
 __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int64_t n0,
                                               char *smem) {
   using T = Traits<P>;
+  using GM = Geom<P, S>;
   using E = typename T::E;
   using Op = typename T::Op;
-  using Acc = typename T::Acc;
+  using Acc = typename GM::Acc;
   using Out = typename T::Out;
   using Plan = DmaPlan<P, S, TA, TB>;
   using OA = typename Plan::OA;
   using OB = typename Plan::OB;
   static_assert(Plan::OK, "shape/layout not offered on the direct-to-LDS path");
-  constexpr int BK = T::BK, KPL = T::KPL, PL = T::PLANES, KS = S::KS;
-  constexpr int KG = BK / 4, KW = KG / KS;
+  constexpr int BK = bk_of<P, S>(), KPL = T::KPL, PL = T::PLANES, KS = S::KS;
+  constexpr int MB = GM::MB, FM = GM::FM, FN = GM::FN, NR = GM::NR;
+  constexpr int KG = GM::KG, KW = KG / KS;
   constexpr int VE = 16 / (int)sizeof(E);
   constexpr int RU = VE < KW ? VE : KW;
   constexpr int U = KW / RU, SPU = RU / KPL;
-  constexpr int NB = S::FM * S::FN, NB1 = NB / 2;
+  constexpr int NB = FM * FN, NB1 = NB / 2;
   constexpr int STAGE = Plan::STAGE, DPW = Plan::PER_WAVE;
+  constexpr int NS = Plan::NS, D = NS - 1;     // ring stages, transfer distance in tiles
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wpos = wave % (S::WM * S::WN), kh = wave / (S::WM * S::WN);
   const int wm = wpos % S::WM, wn = wpos / S::WM;
-  const int lr = lane & 15, lgp = lane >> 4;
+  const int lr = lane % MB, lgp = lane / MB;
 
   const E *Ap[2] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2)};
   const E *Bp[2] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2)};
@@ -215,7 +239,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
 
   const int64_t KT = (g.K + BK - 1) / BK;
   auto issue_tile = [&](int64_t kt) {
-    const int st = (int)(kt % 3);
+    const int st = (int)(kt % NS);
     const int64_t k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
@@ -226,25 +250,25 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     }
   };
 
-  Acc acc[S::FM][S::FN];
+  Acc acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < S::FM; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
+    for (int j = 0; j < FN; ++j) acc[i][j] = Acc{};
 
   using Unit = VecT<E, RU>;
-  Unit fa[2][PL][S::FM], fb[2][PL][S::FN];
+  Unit fa[2][PL][FM], fb[2][PL][FN];
   auto read_unit = [&](int st, int u, auto buf_tag) {
     constexpr int b = decltype(buf_tag)::value;
     const int koff = lgp * KG + kh * KW + u * RU;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
 #pragma unroll
-      for (int i = 0; i < S::FM; ++i)
-        fa[b][pl][i] = OA::template read<RU>(regA(st, pl), wm * S::WTM + i * 16 + lr, koff);
+      for (int i = 0; i < FM; ++i)
+        fa[b][pl][i] = OA::template read<RU>(regA(st, pl), wm * S::WTM + i * MB + lr, koff);
 #pragma unroll
-      for (int j = 0; j < S::FN; ++j)
-        fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * 16 + lr, koff);
+      for (int j = 0; j < FN; ++j)
+        fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * MB + lr, koff);
     }
   };
   auto op_of = [](const Unit &u, int step) {
@@ -262,7 +286,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   auto prep_tile = [&](int64_t kt) {
     pend.on = kt < KT;
     if (!pend.on) return;
-    const int st = (int)(kt % 3);
+    const int st = (int)(kt % NS);
     pend.k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
@@ -306,11 +330,11 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
          constexpr int x = lo + m % NX;
          if constexpr (SLOT >= 0) maybe_issue(std::integral_constant<int, SLOT + m>{});
          if constexpr (PL == 2 && term == 0)
-           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][1][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
+           mfma(acc[x / FN][x % FN], op_of(fa[b][1][x / FN], st), op_of(fb[b][0][x % FN], st));
          else if constexpr (PL == 2 && term == 1)
-           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][1][x % S::FN], st));
+           mfma(acc[x / FN][x % FN], op_of(fa[b][0][x / FN], st), op_of(fb[b][1][x % FN], st));
          else
-           mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
+           mfma(acc[x / FN][x % FN], op_of(fa[b][0][x / FN], st), op_of(fb[b][0][x % FN], st));
        }()), ...);
     }(std::make_integer_sequence<int, SPU * (PL == 2 ? 3 : 1) * NX>{});
   };
@@ -318,13 +342,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   using INB1 = std::integral_constant<int, NB1>;
   using INB = std::integral_constant<int, NB>;
 
-  // One K-tile: issue the transfers two tiles ahead, MFMAs on this tile,
+  // One K-tile: issue the transfers D tiles ahead, MFMAs on this tile,
   // retire the next tile's transfers, barrier, first fragments of the next
   // tile under the last half of this tile's MFMAs.
   auto ktile = [&](auto p0_tag, int64_t kt) {
     constexpr int P0 = decltype(p0_tag)::value;
-    const int cur = (int)(kt % 3);
-    prep_tile(kt + 2);
+    const int cur = (int)(kt % NS);
+    prep_tile(kt + D);
     [&]<int... u>(std::integer_sequence<int, u...>) {
       ((read_unit(cur, u + 1, std::integral_constant<int, (P0 + u + 1) & 1>{}),
         mma_unit_s(std::integral_constant<int, (P0 + u) & 1>{}, I0{}, INB{},
@@ -334,17 +358,17 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     mma_unit_s(std::integral_constant<int, PLU>{}, I0{}, INB1{},
                std::integral_constant<int, (U - 1) * MPB * NB>{});
     if (kt + 1 < KT) {
-      if (kt + 2 < KT) wait_vm_lgkm0<DPW>();   // tile kt+2 may stay in flight
+      if (kt + D < KT) wait_vm_lgkm0<(D - 1) * DPW>();   // tiles after kt+1 may stay in flight
       else wait_vm_lgkm0<0>();
       raw_barrier();
-      read_unit((int)((kt + 1) % 3), 0, std::integral_constant<int, (P0 + U) & 1>{});
+      read_unit((int)((kt + 1) % NS), 0, std::integral_constant<int, (P0 + U) & 1>{});
     }
     mma_unit_s(std::integral_constant<int, PLU>{}, INB1{}, INB{}, std::integral_constant<int, -1>{});
   };
 
   if (KT > 0) {
     issue_tile(0);
-    if (KT > 1) {
+    if (D >= 2 && KT > 1) {
       issue_tile(1);
       wait_vm_lgkm0<DPW>();
     } else {
@@ -374,22 +398,22 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
       for (int h = 1; h < KS; ++h) {
         if (wn == col && kh == h) {
 #pragma unroll
-          for (int i = 0; i < S::FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < S::FN; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
-                red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane] = acc[i][j][q];
+              for (int q = 0; q < NR; ++q)
+                red[(((wm * FM + i) * FN + j) * NR + q) * 64 + lane] = acc[i][j][q];
         }
         __syncthreads();
         if (wn == col && kh == 0) {
 #pragma unroll
-          for (int i = 0; i < S::FM; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < S::FN; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
-                acc[i][j][q] += red[(((wm * S::FM + i) * S::FN + j) * 4 + q) * 64 + lane];
+              for (int q = 0; q < NR; ++q)
+                acc[i][j][q] += red[(((wm * FM + i) * FN + j) * NR + q) * 64 + lane];
         }
         __syncthreads();
       }
@@ -397,16 +421,16 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     if (kh != 0) return;
   }
 
-  constexpr int GRP = T::GRP;
+  constexpr int GRP = T::GRP, LGN = GM::LGN;
   Out *C = reinterpret_cast<Out *>(g.C);
 #pragma unroll
-  for (int i = 0; i < S::FM; ++i) {
+  for (int i = 0; i < FM; ++i) {
 #pragma unroll
-    for (int j = 0; j < S::FN; ++j) {
-      const int64_t col = n0 + wn * S::WTN + j * 16 + lr;
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + wn * S::WTN + j * MB + lr;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t row = m0 + wm * S::WTM + i * 16 + (q / GRP) * 4 * GRP + lgp * GRP + q % GRP;
+      for (int q = 0; q < NR; ++q) {
+        const int64_t row = m0 + wm * S::WTM + i * MB + (q / GRP) * LGN * GRP + lgp * GRP + q % GRP;
         if (row < g.M && col < g.N) C[row * g.ldc + col] = (Out)acc[i][j][q];
       }
     }

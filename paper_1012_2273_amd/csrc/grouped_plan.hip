@@ -39,8 +39,9 @@ static int size_class(int64_t m, int64_t n) {
   return c;
 }
 
-static const int kDefaultPolicy[NCLASS] = {CFG_32x32, CFG_32x32, CFG_64x64, CFG_64x64,
-                                           CFG_64x64, CFG_128x128, CFG_128x128};
+static const int kDefaultPolicy[NCLASS] = {CFG_32x32_K2, CFG_32x32_K2, CFG_64x64_K2,
+                                           CFG_64x64_K2, CFG_64x64_K2, CFG_128x128_K2,
+                                           CFG_128x128_K2};
 
 // Last tuned policy per dtype in this process (used by gemm_grouped).
 static std::mutex g_pol_mu;
@@ -59,6 +60,7 @@ struct gemm_plan {
   uint32_t *d_counter = nullptr;
   int64_t items_cap = 0;
   int32_t n_items = 0;
+  int32_t n_vec = 0;          // items of problems with 16-byte operands (listed first)
   int grid = 0;
   int policy[g355::NCLASS];
   hipGraph_t graph = nullptr;
@@ -72,8 +74,8 @@ static int hip_fail(hipError_t e, const char *what) {
   return set_error(GEMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy) {
-  struct Keyed { int64_t cost; int64_t order; WorkItem w; };
+static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy, int32_t &n_vec) {
+  struct Keyed { int vec; int64_t cost; int64_t order; WorkItem w; };
   std::vector<Keyed> v;
   int64_t order = 0;
   for (size_t i = 0; i < p.probs.size(); ++i) {
@@ -85,17 +87,26 @@ static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy) {
     const int64_t cost = (int64_t)ci.bm * ci.bn * std::max<int64_t>(q.k, 1);
     for (int64_t a = 0; a < tm; ++a)
       for (int64_t b = 0; b < tn; ++b)
-        v.push_back({cost, order++, WorkItem{(int32_t)i, cfg, (int32_t)a, (int32_t)b}});
+        v.push_back({p.dprob_host[i].vec, cost, order++,
+                     WorkItem{(int32_t)i, cfg, (int32_t)a, (int32_t)b}});
   }
-  std::stable_sort(v.begin(), v.end(),
-                   [](const Keyed &x, const Keyed &y) { return x.cost > y.cost; });
+  // 16-byte problems first (their own kernel), each group largest work first
+  std::stable_sort(v.begin(), v.end(), [](const Keyed &x, const Keyed &y) {
+    if (x.vec != y.vec) return x.vec > y.vec;
+    return x.cost > y.cost;
+  });
   std::vector<WorkItem> out(v.size());
-  for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].w;
+  n_vec = 0;
+  for (size_t i = 0; i < v.size(); ++i) {
+    out[i] = v[i].w;
+    n_vec += v[i].vec ? 1 : 0;
+  }
   return out;
 }
 
 static int upload_items(gemm_plan &p, const int *policy) {
-  std::vector<WorkItem> items = plan_items(p, policy);
+  int32_t n_vec = 0;
+  std::vector<WorkItem> items = plan_items(p, policy, n_vec);
   if ((int64_t)items.size() > 0x7fffffff) return set_error(GEMM_EINVAL, "too many tiles");
   if ((int64_t)items.size() > p.items_cap) return set_error(GEMM_ESTATE, "item capacity exceeded");
   if (!items.empty()) {
@@ -104,14 +115,16 @@ static int upload_items(gemm_plan &p, const int *policy) {
     if (e != hipSuccess) return hip_fail(e, "upload work items");
   }
   p.n_items = (int32_t)items.size();
+  p.n_vec = n_vec;
   std::memcpy(p.policy, policy, sizeof(p.policy));
   return GEMM_OK;
 }
 
 static int launch_direct(gemm_plan &p, hipStream_t s) {
   hipError_t e = launch_counter_reset(p.d_counter, s);
-  if (e == hipSuccess) e = launch_grouped(p.prec, p.d_probs, p.d_items, p.n_items, p.d_counter,
-                                          p.grid, s);
+  if (e == hipSuccess)
+    e = launch_grouped(p.prec, p.d_probs, p.d_items, p.n_vec, p.n_items - p.n_vec, p.d_counter,
+                       p.grid, s);
   if (e != hipSuccess) return hip_fail(e, "grouped launch");
   return GEMM_OK;
 }
@@ -179,7 +192,7 @@ static std::string cache_key(const gemm_plan &p) {
 static bool policy_valid(const std::vector<int> &v) {
   if ((int)v.size() != NCLASS) return false;
   for (int x : v)
-    if (x < 0 || x >= CFG_GROUPED_COUNT) return false;
+    if (!cfg_grouped(x)) return false;
   return true;
 }
 
@@ -218,7 +231,7 @@ static int autotune(gemm_plan &p, hipStream_t s, int *policy) {
   if (rc) return rc;
   for (int c = NCLASS - 1; c >= 0; --c) {
     if (!present[c]) continue;
-    for (int cfg = 0; cfg < CFG_GROUPED_COUNT; ++cfg) {
+    for (int cfg : kGroupedCfgs) {
       if (cfg == policy[c]) continue;
       int trial[NCLASS];
       std::memcpy(trial, policy, sizeof(trial));
@@ -331,7 +344,7 @@ int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *pro
     p->dprob_host[i] = to_device(probs[i], es);
     if (probs[i].m > 0 && probs[i].n > 0) {
       int64_t worst = 0;   // most tiles any configuration can produce
-      for (int c = 0; c < CFG_GROUPED_COUNT; ++c) {
+      for (int c : kGroupedCfgs) {
         const CfgInfo &ci = cfg_info(c);
         worst = std::max(worst, ((probs[i].m + ci.bm - 1) / ci.bm) * ((probs[i].n + ci.bn - 1) / ci.bn));
       }

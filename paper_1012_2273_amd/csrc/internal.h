@@ -14,12 +14,16 @@ struct GemmArgs;
 
 // Tile configurations the kernels are instantiated for. The id is the
 // value the tuner and the grouped planner store.
-// Configs below CFG_GROUPED_COUNT use 256 threads and can share the
-// persistent grouped kernel; the others run as single-product launches.
+// Tile configurations. The K-split ones (512 threads: two waves per output
+// position, each taking half of every K-tile) are the ones the persistent
+// grouped kernel offers; every configuration runs as a single product.
 enum TileCfg : int {
-  CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3, CFG_GROUPED_COUNT = 4,
-  CFG_128x128_W8 = 4, CFG_128x128_K2 = 5, CFG_128x64_K2 = 6, CFG_COUNT = 7
+  CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3,
+  CFG_128x128_W8 = 4, CFG_128x128_K2 = 5, CFG_128x64_K2 = 6, CFG_64x64_K2 = 7,
+  CFG_32x32_K2 = 8, CFG_COUNT = 9
 };
+constexpr int kGroupedCfgs[4] = {CFG_128x128_K2, CFG_128x64_K2, CFG_64x64_K2, CFG_32x32_K2};
+bool cfg_grouped(int cfg);
 struct CfgInfo { int bm, bn; const char *name; };
 const CfgInfo &cfg_info(int id);
 bool cfg_supported(int prec, int cfg);
@@ -40,6 +44,13 @@ hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx,
                         uint16_t *hi, uint16_t *lo, int64_t ldo, int64_t out_pad,
                         hipStream_t stream);
 
+// Both operands of the split product in one launch: A (m x k) -> row-major
+// planes (m x kp), B (k x n) -> transposed planes (n x kp); kp a multiple of
+// 8, padding zeroed, plane rows 16-byte aligned.
+hipError_t launch_split_pair(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                             const float *B, int64_t ldb, uint16_t *ahi, uint16_t *alo,
+                             uint16_t *bhi, uint16_t *blo, int64_t kp, hipStream_t stream);
+
 // Grouped: descriptors and tile-queue items live in device memory.
 struct GroupedProblem {          // device-side problem record
   int64_t M, N, K;
@@ -53,8 +64,13 @@ struct WorkItem {                // one output tile
   int32_t cfg;                   // tile config id
   int32_t tm, tn;                // tile coordinates
 };
+// items[0, n_vec) belong to problems with 16-byte operands, the n_scalar
+// items after them to the others; each group has its own persistent kernel
+// and queue counter (counter[0] and counter[kCounterStride]).
+constexpr int kCounterStride = 16;
 hipError_t launch_grouped(int prec, const GroupedProblem *probs, const WorkItem *items,
-                          int32_t n_items, uint32_t *counter, int grid, hipStream_t stream);
+                          int32_t n_vec, int32_t n_scalar, uint32_t *counter, int grid,
+                          hipStream_t stream);
 hipError_t launch_counter_reset(uint32_t *counter, hipStream_t stream);
 int grouped_max_grid(int prec);   // persistent workgroups that fit the device
 

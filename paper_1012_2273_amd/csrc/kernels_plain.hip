@@ -74,6 +74,8 @@ using S32x32 = Shape<32, 32, 2, 2>;
 using S128x128w8 = Shape<128, 128, 4, 2>;
 using S128x128k2 = Shape<128, 128, 2, 2, 2>;
 using S128x64k2 = Shape<128, 64, 2, 2, 2>;
+using S64x64k2 = Shape<64, 64, 2, 2, 2>;
+using S32x32k2 = Shape<32, 32, 2, 2, 2>;
 
 template <int P>
 static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipStream_t s) {
@@ -85,6 +87,8 @@ static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipSt
     case CFG_128x128_W8: return by_layout<P, S128x128w8>(layout, vec, a, s);
     case CFG_128x128_K2: return by_layout<P, S128x128k2>(layout, vec, a, s);
     case CFG_128x64_K2: return by_layout<P, S128x64k2>(layout, vec, a, s);
+    case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, a, s);
+    case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, a, s);
   }
   return hipErrorInvalidValue;
 }
