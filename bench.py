@@ -38,8 +38,11 @@ HBM_PEAK = 8000.0                                    # GB/s
 METRIC = "GFLOP/s (2N^3/t) at N=2000 FP64 vs split-BF16, at stated rel. error"
 ALL_PATHS = ["fp64", "split", "fp32", "bf16", "backward", "grouped"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp64_n2000.json")
+# the binary64 kernel's code and the host choice of its tile shape
 KERNEL_SOURCES = ["paper_1012_2273_amd/csrc/gemm_tile.hpp",
-                  "paper_1012_2273_amd/csrc/kernels_plain.hip"]
+                  "paper_1012_2273_amd/csrc/gemm_tile_dma.hpp",
+                  "paper_1012_2273_amd/csrc/kernels_plain.hip",
+                  "paper_1012_2273_amd/csrc/gemm_api.hip"]
 
 
 def kernel_hash():
