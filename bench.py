@@ -10,7 +10,9 @@ seeded synthetic inputs:
   bf16     gemm_plain bfloat16 inputs, binary32 output, N = 2000
   backward gemm_backward binary32 (dA and dB), N = 2048, dC = W
   grouped  512 products, N log-uniform in [10, 2000], binary64, one replay
-           of the captured persistent launch (tuned policy)
+           of the captured persistent launch (tuned policy); the same 512
+           products as 512 single launches are timed after the step loop
+           and reported beside it (loop_ms, speedup_vs_loop)
 Each path is bracketed by HIP events on torch's current stream (the stream
 the kernels run on); the step loop is bracketed by device synchronisation.
 ``value`` is the binary64 rate 2N^3/t at N = 2000; the split rate and every
@@ -198,6 +200,28 @@ def main():
     ms = {p: float(np.mean([a.elapsed_time(b) for a, b in evs[p]])) for p in order}
     ms_min = {p: float(np.min([a.elapsed_time(b) for a, b in evs[p]])) for p in order}
 
+    # ------------------------------------- grouped versus one launch per product
+    loop = None
+    if "grouped" in order:
+        gC = [torch.empty_like(a) for a in gA]
+
+        def run_loop():
+            for a, b, c in zip(gA, gB, gC):
+                G.gemm_plain(a, b, c)
+        run_loop()
+        torch.cuda.synchronize()
+        le = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run_loop()
+            e1.record(stream)
+            le.append((e0, e1))
+        torch.cuda.synchronize()
+        loop = float(np.mean([a.elapsed_time(b) for a, b in le]))
+        del gC
+
     # ---------------------------------------------------------- error check
     import oracle
     errs = {}
@@ -262,6 +286,10 @@ def main():
         if p in errs:
             d["rel_err"] = float(f"{errs[p]:.3e}")
         paths_out[p] = d
+    if loop is not None:
+        paths_out["grouped"]["loop_ms"] = round(loop, 4)
+        paths_out["grouped"]["loop_gflops"] = round(work["grouped"][1] / (loop * 1e-3) / 1e9, 2)
+        paths_out["grouped"]["speedup_vs_loop"] = round(loop / ms["grouped"], 3)
     if "split" in paths_out:
         paths_out["split"]["mfma_util_bf16"] = round(
             6.0 * N ** 3 / (ms["split"] * 1e-3) / 1e12 / PEAK["bf16"], 4)

@@ -14,16 +14,23 @@
 //    elements, 16-byte chunks XOR-swizzled per row (chunk c of row r holds
 //    global chunk c ^ swz(r)) so that sixteen lanes reading the same K
 //    offset of sixteen rows hit distinct banks.
-//  * MN-contiguous operand (A transposed, B not transposed), 4- and 8-byte
-//    elements only: rows of R elements, one per k, as in memory; a lane's
-//    MFMA operand is one element, read per step from row k.
+//  * MN-contiguous operand (A transposed, B not transposed): rows of R
+//    elements, one per k, as in memory. 4- and 8-byte elements: a lane's
+//    MFMA operand is one element, read per step from row k. 16-bit
+//    elements: 16-byte chunks XOR-swizzled per row in pairs (32-byte
+//    column blocks stay whole), read with the transposing LDS read
+//    (ds_read_b64_tr_b16), which hands each lane four consecutive k of one
+//    column: within a group of 16 lanes, lane 4a + e receives element e of
+//    the 8 bytes addressed by lanes a, a + 4, a + 8, a + 12, so lanes
+//    a + 4j address row k + j at column 4a of the group's 16 columns.
 #pragma once
 
 #include "gemm_tile.hpp"
 
 namespace g355 {
 
-#define G355_LDS(p) ((__attribute__((address_space(3))) void *)(p))
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 // s_waitcnt encodings (gfx9): vmcnt in bits [3:0] and [15:14], expcnt [6:4],
 // lgkmcnt [11:8]; unused counters at their maximum.
@@ -84,14 +91,24 @@ struct DmaOp {
   static constexpr int NW = NT / 64;
   static constexpr int PERW = NI / NW;               // transfers per wave per tile
   static constexpr int BYTES = CHUNKS * 16;
+  static constexpr bool TR = !KC && ES == 2;         // transposing reads
   static constexpr bool OK = (RB % 16 == 0) && (CHUNKS % 64 == 0) && (NI % NW == 0) &&
-                             (PERW >= 1) && (KC || ES >= 4) && (!KC || RB <= 256);
+                             (PERW >= 1) && (KC || ES >= 4 || (TR && CPR % 2 == 0)) &&
+                             (!KC || RB <= 256);
 
   uint32_t off[PERW > 0 ? PERW : 1];
   int32_t kk[PERW > 0 ? PERW : 1];   // K index of the chunk (first element)
   bool rok[PERW > 0 ? PERW : 1];     // M/N index inside the matrix
 
   __device__ __forceinline__ static int swz(int r) { return ((r * RB) >> 8) % CPR; }
+  // MN rows of 16-bit elements: rows k .. k+3 of one transposing read put
+  // their 32-byte column blocks in four different 32-byte bank groups.
+  __device__ __forceinline__ static int swzm(int r) {
+    if constexpr (!TR) return 0;
+    else if constexpr (CPR >= 8) return 2 * (r % 4);
+    else if constexpr (CPR >= 4) return 2 * (r % 2);
+    else return 0;
+  }
 
   __device__ __forceinline__ void init(int64_t ld, int64_t r0, int64_t rtot, int wave, int lane) {
 #pragma unroll
@@ -104,7 +121,7 @@ struct DmaOp {
         kk[j] = k;
         rok[j] = r0 + r < rtot;
       } else {
-        const int m = c * V;
+        const int m = (c ^ swzm(r)) * V;
         off[j] = (uint32_t)(((int64_t)r * ld + m) * ES);
         kk[j] = r;
         rok[j] = r0 + m < rtot;
@@ -136,13 +153,29 @@ struct DmaOp {
   }
 
   // RU consecutive K elements (K offset koff, a multiple of RU) of LDS row
-  // `row` (KC) or column `row` (MN).
+  // `row` (KC) or column `row` (MN). For TR the 16 lanes of a group must
+  // ask for 16 consecutive columns starting at a multiple of 16, lane i for
+  // column start + i, all at the same koff.
   template <int RU>
   __device__ __forceinline__ static VecT<E, RU> read(const char *region, int row, int koff) {
     VecT<E, RU> v;
     if constexpr (KC) {
       const int c = koff / V, e0 = koff % V;
       v = *reinterpret_cast<const VecT<E, RU> *>(region + row * RB + ((c ^ swz(row)) * 16) + e0 * ES);
+    } else if constexpr (TR) {
+      static_assert(RU % 4 == 0, "a transposing read delivers four K elements");
+      const int l16 = (int)(threadIdx.x & 15);
+      const int col = row - l16 + 4 * (l16 & 3);      // the 8 bytes this lane addresses
+      const int cc = col / V, ce = col % V;
+#pragma unroll
+      for (int h = 0; h < RU / 4; ++h) {
+        const int k = koff + 4 * h + (l16 >> 2);
+        const char *p = region + k * RB + ((cc ^ swzm(k)) * 16) + ce * ES;
+        const s16x4 t = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (__attribute__((address_space(3))) s16x4 *)(p));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v.e[4 * h + j] = (E)t[j];
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < RU; ++e)
@@ -180,8 +213,7 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   static constexpr int NS = 3 * STAGE <= 144 * 1024 ? 3 : 2;
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
   static constexpr bool OK = OA::OK && OB::OK && Geom<P, S>::OK && PER_WAVE < 32 &&
-                             NS * STAGE <= 160 * 1024 &&
-                             (TA ? T::KPL == 1 : true) && (TB ? true : T::KPL == 1);
+                             NS * STAGE <= 160 * 1024;
 };
 
 template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr bool dma_ok() {
