@@ -293,12 +293,13 @@ def main():
     if "split" in paths_out:
         paths_out["split"]["mfma_util_bf16"] = round(
             6.0 * N ** 3 / (ms["split"] * 1e-3) / 1e12 / PEAK["bf16"], 4)
-    t_fp64 = ms["fp64"] * 1e-3
+    # a run restricted to other paths (--paths) reports no headline value
+    t_fp64 = ms["fp64"] * 1e-3 if "fp64" in ms else float("nan")
     achieved = 2.0 * N ** 3 / t_fp64 / 1e12
     traffic = traffic_for_current_kernel()
     line = {
         "metric": METRIC,
-        "value": round(2.0 * N ** 3 / t_fp64 / 1e9, 2),
+        "value": round(2.0 * N ** 3 / t_fp64 / 1e9, 2) if "fp64" in ms else None,
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -314,12 +315,13 @@ def main():
                    "N": N, "paths": order},
         "split_bf16": {"value": paths_out.get("split", {}).get("gflops"),
                        "rel_err": paths_out.get("split", {}).get("rel_err"),
-                       "vs_fp64": (round(ms["fp64"] / ms["split"], 2) if "split" in ms else None)},
-        "fp64_rel_err": paths_out["fp64"].get("rel_err"),
+                       "vs_fp64": (round(ms["fp64"] / ms["split"], 2)
+                                 if "split" in ms and "fp64" in ms else None)},
+        "fp64_rel_err": paths_out.get("fp64", {}).get("rel_err"),
         "paths": paths_out,
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
-                     "traffic": traffic},
+        "roofline": ({"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
+                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
+                      "traffic": traffic} if "fp64" in ms else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

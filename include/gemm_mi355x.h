@@ -74,7 +74,8 @@ int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k,
 
 /*
  * gemm_split_workspace_size -- bytes of device workspace gemm_split needs
- * for this shape (the four bfloat16 operand planes, 256-byte aligned).
+ * for this shape (the four bfloat16 operand planes, rows of k rounded up to
+ * 8 elements at a pitch rounded up to 64 elements, planes 256-byte aligned).
  * Returns 0 for negative sizes.
  */
 size_t gemm_split_workspace_size(int64_t m, int64_t n, int64_t k);

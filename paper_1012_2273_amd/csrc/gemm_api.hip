@@ -88,7 +88,8 @@ static int choose_cfg(int prec, int64_t m, int64_t n) {
       if (t128 >= big) return CFG_128x64_K2;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     case PREC_BF16:
-      if (t128 >= big) return CFG_128x64;
+      if (t128 >= 2 * cus) return CFG_128x128;
+      if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     default:  // split
       if (t128 >= big) return CFG_128x128_W8;
@@ -208,11 +209,17 @@ static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 // Workspace layout: A_hi | A_lo (m x kp) then B_hi | B_lo (n x kp), kp = k
 // rounded up to 8 elements (16 bytes) so every plane row is 16-byte aligned;
 // each plane starts on a 256-byte boundary.
-static void split_layout(int64_t m, int64_t n, int64_t k, int64_t &kp, size_t off[4],
-                         size_t &total) {
+// Plane rows hold kp = k rounded up to 8 elements (zeros past k) at a pitch
+// of ldp = kp rounded up to 64 elements: every row starts on a 128-byte
+// line, so a 16-byte-per-lane transfer of a K-tile touches whole lines
+// (a 4000-byte pitch at k = 2000 made most K-chunks straddle two lines and
+// cost the product 17% at N = 2000).
+static void split_layout(int64_t m, int64_t n, int64_t k, int64_t &kp, int64_t &ldp,
+                         size_t off[4], size_t &total) {
   kp = round_up(k > 0 ? k : 1, 8);
-  const size_t a_bytes = (size_t)round_up(m * kp * 2, 256);
-  const size_t b_bytes = (size_t)round_up(n * kp * 2, 256);
+  ldp = round_up(kp, 64);
+  const size_t a_bytes = (size_t)round_up(m * ldp * 2, 256);
+  const size_t b_bytes = (size_t)round_up(n * ldp * 2, 256);
   off[0] = 0;
   off[1] = a_bytes;
   off[2] = 2 * a_bytes;
@@ -222,9 +229,9 @@ static void split_layout(int64_t m, int64_t n, int64_t k, int64_t &kp, size_t of
 
 size_t gemm_split_workspace_size(int64_t m, int64_t n, int64_t k) {
   if (m < 0 || n < 0 || k < 0) return 0;
-  int64_t kp;
+  int64_t kp, ldp;
   size_t off[4], total;
-  split_layout(m, n, k, kp, off, total);
+  split_layout(m, n, k, kp, ldp, off, total);
   return total;
 }
 
@@ -257,9 +264,9 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
       (rc = check_mat("C", C, m, n, ldc)))
     return rc;
   if (m == 0 || n == 0) return GEMM_OK;
-  int64_t kp;
+  int64_t kp, ldp;
   size_t off[4], total;
-  split_layout(m, n, k, kp, off, total);
+  split_layout(m, n, k, kp, ldp, off, total);
   if (workspace == nullptr || workspace_bytes < total)
     return set_error(GEMM_EWORKSPACE, "need " + std::to_string(total) + " bytes, got " +
                                           std::to_string(workspace_bytes));
@@ -273,10 +280,10 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
     // planes carry zeros in the padding columns [k, kp), so the product may
     // run over kp (a whole number of 8-element vectors) unchanged
     if ((rc = check_ld_range("A", lda, 4)) || (rc = check_ld_range("B", ldb, 4))) return rc;
-    hipError_t e = launch_split_pair(m, n, k, A, lda, B, ldb, ahi, alo, bhi, blo, kp, s);
+    hipError_t e = launch_split_pair(m, n, k, A, lda, B, ldb, ahi, alo, bhi, blo, kp, ldp, s);
     if (e != hipSuccess) return hip_fail(e, "split launch");
   }
-  GemmArgs a{m, n, k > 0 ? kp : 0, ahi, kp, bhi, kp, alo, blo, C, ldc};
+  GemmArgs a{m, n, k > 0 ? kp : 0, ahi, ldp, bhi, ldp, alo, blo, C, ldc};
   return run_product(PREC_SPLIT, LAYOUT_NT, a, 2, s);
 }
 

@@ -3,8 +3,8 @@
 // Same product and MFMA mapping as gemm_tile (Hasta and Mutiara, Section 3.1,
 // Algorithm 1, reduction blocked over K-tiles), different data movement:
 // operands go HBM/L2 -> LDS with `buffer_load_dwordx4 ... lds` (no VGPR
-// staging), into a ring of three LDS stages, two K-tiles ahead of the
-// MFMAs. Waits are explicit: every wave issues the same number of 16-byte
+// staging), into a ring of two to eight LDS stages, several K-tiles ahead
+// of the MFMAs. Waits are explicit: every wave issues the same number of 16-byte
 // transfers per K-tile, so `s_waitcnt vmcnt(n)` with n = one tile's count
 // retires exactly the tile about to be read; a barrier then makes all
 // waves' transfers visible.
@@ -78,8 +78,9 @@ __device__ __forceinline__ void raw_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// One operand plane of one K-tile: R rows (M or N) x BK.
-template <typename E, int R, int BK, int NT, bool KC>
+// One operand plane of one K-tile: R rows (M or N) x BK. LG: K rows
+// between the lane groups of one LDS read (MN layout swizzle).
+template <typename E, int R, int BK, int NT, bool KC, int LG>
 struct DmaOp {
   static constexpr int ES = (int)sizeof(E);
   static constexpr int V = 16 / ES;                  // elements per chunk
@@ -94,20 +95,27 @@ struct DmaOp {
   static constexpr bool TR = !KC && ES == 2;         // transposing reads
   static constexpr bool OK = (RB % 16 == 0) && (CHUNKS % 64 == 0) && (NI % NW == 0) &&
                              (PERW >= 1) && (KC || ES >= 4 || (TR && CPR % 2 == 0)) &&
-                             (!KC || RB <= 256);
+                             (!KC || RB <= 256) && (KC || (CPR & (CPR - 1)) == 0) && LG >= 1;
 
   uint32_t off[PERW > 0 ? PERW : 1];
   int32_t kk[PERW > 0 ? PERW : 1];   // K index of the chunk (first element)
   bool rok[PERW > 0 ? PERW : 1];     // M/N index inside the matrix
 
   __device__ __forceinline__ static int swz(int r) { return ((r * RB) >> 8) % CPR; }
-  // MN rows of 16-bit elements: rows k .. k+3 of one transposing read put
+  // MN rows. 16-bit elements: rows k .. k+3 of one transposing read put
   // their 32-byte column blocks in four different 32-byte bank groups.
+  // 4- and 8-byte elements: the four lane groups of a read take rows LG
+  // apart, 16 consecutive elements each; shifting row k's chunks by
+  // (k / LG) % 4 such spans puts the four groups on different banks.
   __device__ __forceinline__ static int swzm(int r) {
-    if constexpr (!TR) return 0;
-    else if constexpr (CPR >= 8) return 2 * (r % 4);
-    else if constexpr (CPR >= 4) return 2 * (r % 2);
-    else return 0;
+    if constexpr (KC) return 0;
+    else if constexpr (TR) {
+      if constexpr (CPR >= 8) return 2 * (r % 4);
+      else if constexpr (CPR >= 4) return 2 * (r % 2);
+      else return 0;
+    } else {
+      return (((r / LG) & 3) * ES) & (CPR - 1);
+    }
   }
 
   __device__ __forceinline__ void init(int64_t ld, int64_t r0, int64_t rtot, int wave, int lane) {
@@ -177,9 +185,12 @@ struct DmaOp {
         for (int j = 0; j < 4; ++j) v.e[4 * h + j] = (E)t[j];
       }
     } else {
+      const int cc = row / V, ce = row % V;
 #pragma unroll
-      for (int e = 0; e < RU; ++e)
-        v.e[e] = *reinterpret_cast<const E *>(region + (koff + e) * RB + row * ES);
+      for (int e = 0; e < RU; ++e) {
+        const int k = koff + e;
+        v.e[e] = *reinterpret_cast<const E *>(region + k * RB + ((cc ^ swzm(k)) * 16) + ce * ES);
+      }
     }
     return v;
   }
@@ -202,16 +213,39 @@ template <int P, class S> struct Geom {
                              FM >= 1 && FN >= 1;
 };
 
+// LDS budget of the ring on the 16-bit precisions: 48 KiB keeps three
+// workgroups of a 128 x 128 bf16 tile on a CU, which measured faster than
+// deeper rings at one or two workgroups per CU (N = 2000 ... 8192).
+#ifndef G355_RING16_KB
+#define G355_RING16_KB 48
+#endif
+constexpr int kRing16 = G355_RING16_KB * 1024;
+
+// Wait until at most n K-tiles of DPW transfers each are still in flight
+// (0 <= n <= MAXT; n is the same on every lane).
+template <int DPW, int MAXT> __device__ __forceinline__ void wait_tiles(int n) {
+  [&]<int... t>(std::integer_sequence<int, t...>) {
+    ((void)(n == t ? (wait_vm_lgkm0<t * DPW>(), 0) : 0), ...);
+  }(std::make_integer_sequence<int, MAXT + 1>{});
+}
+
 template <int P, class S, bool TA, bool TB> struct DmaPlan {
   using T = Traits<P>;
   using E = typename T::E;
-  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA>;
-  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB>;
+  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA, Geom<P, S>::KG>;
+  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB, Geom<P, S>::KG>;
   static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
-  // ring depth: three stages (transfers two K-tiles ahead) when they fit in
-  // 144 KiB of the 160 KiB LDS, else two (one tile ahead)
-  static constexpr int NS = 3 * STAGE <= 144 * 1024 ? 3 : 2;
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
+  // Ring depth: transfers run NS - 1 K-tiles ahead of the MFMAs. binary64
+  // and binary32: three stages when they fit in 144 KiB of the 160 KiB LDS,
+  // else two. 16-bit: as many stages as fit in the ring budget (2 to 8);
+  // small tiles get deeper rings, large tiles keep several workgroups per
+  // CU. vmcnt (6 bits) bounds the transfers a wave may leave outstanding.
+  static constexpr int FIT = (T::KPL == 8 ? kRing16 : 144 * 1024) / STAGE;
+  static constexpr int VMAX = 1 + 63 / (PER_WAVE > 0 ? PER_WAVE : 1);
+  static constexpr int NS0 = T::KPL == 8 ? (FIT < 8 ? FIT : 8) : (FIT >= 3 ? 3 : 2);
+  static constexpr int NS1 = NS0 < VMAX ? NS0 : VMAX;
+  static constexpr int NS = NS1 < 2 ? 2 : NS1;
   static constexpr bool OK = OA::OK && OB::OK && Geom<P, S>::OK && PER_WAVE < 32 &&
                              NS * STAGE <= 160 * 1024;
 };
@@ -270,8 +304,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   auto regB = [&](int st, int pl) { return smem + st * STAGE + PL * OA::BYTES + pl * OB::BYTES; };
 
   const int64_t KT = (g.K + BK - 1) / BK;
-  auto issue_tile = [&](int64_t kt) {
-    const int st = (int)(kt % NS);
+  auto issue_tile = [&](int64_t kt, int st) {
     const int64_t k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
@@ -307,18 +340,23 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     return *reinterpret_cast<const Op *>(&u.e[step * KPL]);
   };
 
-  // Transfers of the K-tile two ahead are spread over the MFMAs issued
-  // before the barrier: a 1 KiB transfer occupies the CU's address unit for
-  // many cycles, and a wave queued behind it issues no MFMA meanwhile.
-  // Transfer k goes right before pre-barrier MFMA number k * NPRE / DPW.
+  // Issue of the transfers of the K-tile D ahead. binary64/binary32: spread
+  // over the first half of the MFMAs issued before the barrier (a 1 KiB
+  // transfer occupies the CU's address unit for many cycles, and a wave
+  // queued behind it issues no MFMA meanwhile; transfer k goes right before
+  // pre-barrier MFMA number k * NPRE / (2 DPW)), so the last one still has
+  // half a K-tile to land before the barrier (spreading over the whole tile
+  // measured 4-5% slower). 16-bit: all at the start of the K-tile, whose
+  // MFMAs take about as long as the transfers themselves at the L2 -> CU
+  // rate (measured 8-10% faster than spreading).
+  constexpr bool BURST = KPL == 8;
   constexpr int MPB = SPU * (PL == 2 ? 3 : 1);          // MFMAs per block per unit
   constexpr int NPRE = MPB * ((U - 1) * NB + NB1);       // pre-barrier MFMAs per tile
   struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; bool on; };
   Pending pend;
-  auto prep_tile = [&](int64_t kt) {
+  auto prep_tile = [&](int64_t kt, int st) {
     pend.on = kt < KT;
     if (!pend.on) return;
-    const int st = (int)(kt % NS);
     pend.k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
@@ -341,11 +379,12 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
         ob.issue_one(r - OA::PERW, pend.sb[pl], pend.k0, g.K, pend.lb[pl], wave);
     }
   };
-  // pre-barrier MFMA number n: issue every transfer k with k * NPRE / DPW == n
+  // pre-barrier MFMA number n: issue every transfer k with k * NPRE / (2 DPW) == n
   auto maybe_issue = [&](auto n_tag) {
     constexpr int n = decltype(n_tag)::value;
+    if constexpr (BURST) return;
     [&]<int... k>(std::integer_sequence<int, k...>) {
-      ((void)((k * NPRE / DPW == n) ? (issue_k(std::integral_constant<int, k>{}), 0) : 0), ...);
+      ((void)((k * NPRE / (2 * DPW) == n) ? (issue_k(std::integral_constant<int, k>{}), 0) : 0), ...);
     }(std::make_integer_sequence<int, DPW>{});
   };
   // MFMAs of blocks [lo, hi) of a unit; SLOT is the pre-barrier number of the
@@ -374,13 +413,19 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   using INB1 = std::integral_constant<int, NB1>;
   using INB = std::integral_constant<int, NB>;
 
-  // One K-tile: issue the transfers D tiles ahead, MFMAs on this tile,
-  // retire the next tile's transfers, barrier, first fragments of the next
-  // tile under the last half of this tile's MFMAs.
-  auto ktile = [&](auto p0_tag, int64_t kt) {
+  // One K-tile (stage cur): issue the transfers D tiles ahead (into the
+  // stage read one tile ago), MFMAs on this tile, retire the next tile's
+  // transfers, barrier, first fragments of the next tile under the last
+  // half of this tile's MFMAs.
+  auto ktile = [&](auto p0_tag, int64_t kt, int cur) {
     constexpr int P0 = decltype(p0_tag)::value;
-    const int cur = (int)(kt % NS);
-    prep_tile(kt + D);
+    const int nxt = cur + 1 == NS ? 0 : cur + 1;
+    prep_tile(kt + D, cur == 0 ? NS - 1 : cur - 1);
+    if constexpr (BURST) {
+      [&]<int... k>(std::integer_sequence<int, k...>) {
+        (issue_k(std::integral_constant<int, k>{}), ...);
+      }(std::make_integer_sequence<int, DPW>{});
+    }
     [&]<int... u>(std::integer_sequence<int, u...>) {
       ((read_unit(cur, u + 1, std::integral_constant<int, (P0 + u + 1) & 1>{}),
         mma_unit_s(std::integral_constant<int, (P0 + u) & 1>{}, I0{}, INB{},
@@ -390,30 +435,36 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     mma_unit_s(std::integral_constant<int, PLU>{}, I0{}, INB1{},
                std::integral_constant<int, (U - 1) * MPB * NB>{});
     if (kt + 1 < KT) {
-      if (kt + D < KT) wait_vm_lgkm0<(D - 1) * DPW>();   // tiles after kt+1 may stay in flight
-      else wait_vm_lgkm0<0>();
+      // tiles kt+2 .. min(kt+D, KT-1) may stay in flight
+      const int64_t rest = KT - 2 - kt;
+      wait_tiles<DPW, D - 1>(rest < D - 1 ? (int)rest : D - 1);
       raw_barrier();
-      read_unit((int)((kt + 1) % NS), 0, std::integral_constant<int, (P0 + U) & 1>{});
+      read_unit(nxt, 0, std::integral_constant<int, (P0 + U) & 1>{});
     }
     mma_unit_s(std::integral_constant<int, PLU>{}, INB1{}, INB{}, std::integral_constant<int, -1>{});
   };
 
   if (KT > 0) {
-    issue_tile(0);
-    if (D >= 2 && KT > 1) {
-      issue_tile(1);
-      wait_vm_lgkm0<DPW>();
-    } else {
-      wait_vm_lgkm0<0>();
-    }
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+      if (t < KT) issue_tile(t, t);
+    wait_tiles<DPW, D - 1>(KT < D ? (int)KT - 1 : D - 1);   // tile 0 has landed
     raw_barrier();
     read_unit(0, 0, I0{});
+    int st = 0;
     if constexpr (U % 2 == 0) {
-      for (int64_t kt = 0; kt < KT; ++kt) ktile(I0{}, kt);
+      for (int64_t kt = 0; kt < KT; ++kt) {
+        ktile(I0{}, kt, st);
+        st = st + 1 == NS ? 0 : st + 1;
+      }
     } else {
       for (int64_t kt = 0; kt < KT; kt += 2) {
-        ktile(I0{}, kt);
-        if (kt + 1 < KT) ktile(std::integral_constant<int, 1>{}, kt + 1);
+        ktile(I0{}, kt, st);
+        st = st + 1 == NS ? 0 : st + 1;
+        if (kt + 1 < KT) {
+          ktile(std::integral_constant<int, 1>{}, kt + 1, st);
+          st = st + 1 == NS ? 0 : st + 1;
+        }
       }
     }
     // every wave has finished its LDS reads before the stages are reused

@@ -49,7 +49,8 @@ hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 // 8, padding zeroed, plane rows 16-byte aligned.
 hipError_t launch_split_pair(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                              const float *B, int64_t ldb, uint16_t *ahi, uint16_t *alo,
-                             uint16_t *bhi, uint16_t *blo, int64_t kp, hipStream_t stream);
+                             uint16_t *bhi, uint16_t *blo, int64_t kp, int64_t ldp,
+                             hipStream_t stream);
 
 // Grouped: descriptors and tile-queue items live in device memory.
 struct GroupedProblem {          // device-side problem record

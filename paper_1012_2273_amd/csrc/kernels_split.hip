@@ -173,13 +173,14 @@ split_pair_kernel(SplitJob a, SplitJob b, int64_t na) {
 
 hipError_t launch_split_pair(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                              const float *B, int64_t ldb, uint16_t *ahi, uint16_t *alo,
-                             uint16_t *bhi, uint16_t *blo, int64_t kp, hipStream_t stream) {
+                             uint16_t *bhi, uint16_t *blo, int64_t kp, int64_t ldp,
+                             hipStream_t stream) {
   if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
-  if (kp % 8 != 0 || ((uintptr_t)bhi % 16) || ((uintptr_t)blo % 16) || ((uintptr_t)ahi % 8) ||
-      ((uintptr_t)alo % 8))
+  if (kp % 8 != 0 || ldp % 8 != 0 || ldp < kp || ((uintptr_t)bhi % 16) || ((uintptr_t)blo % 16) ||
+      ((uintptr_t)ahi % 8) || ((uintptr_t)alo % 8))
     return hipErrorInvalidValue;
-  SplitJob a{A, lda, m, k, kp, ahi, alo, kp, (kp + 63) / 64};
-  SplitJob b{B, ldb, k, n, kp, bhi, blo, kp, (n + 63) / 64};
+  SplitJob a{A, lda, m, k, kp, ahi, alo, ldp, (kp + 63) / 64};
+  SplitJob b{B, ldb, k, n, kp, bhi, blo, ldp, (n + 63) / 64};
   const int64_t na = ((m + 63) / 64) * a.tiles_c;
   const int64_t nb = ((kp + 63) / 64) * b.tiles_c;
   if (na + nb > 0x7fffffff) return hipErrorInvalidValue;

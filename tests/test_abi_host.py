@@ -79,8 +79,10 @@ def test_split_workspace_size(lib):
     assert lib.gemm_split_workspace_size(-1, 2, 2) == 0
     s = lib.gemm_split_workspace_size(2000, 2000, 2000)
     assert s >= 2 * 2 * 2000 * 2000 * 2 and s % 256 == 0
-    # k padded to 8 elements per plane row
+    # plane rows padded to a 64-element (128-byte) pitch, planes to 256 bytes
     assert lib.gemm_split_workspace_size(1, 1, 1) == 4 * 256
+    assert lib.gemm_split_workspace_size(3, 5, 65) == 2 * 768 + 2 * 1280
+    assert lib.gemm_split_workspace_size(2000, 2000, 2000) == 4 * 2000 * 2048 * 2
 
 
 def test_split_validation(lib):
