@@ -81,12 +81,13 @@ static int choose_cfg(int prec, int64_t m, int64_t n) {
   const int64_t big = cus * 200 / 256, mid = cus * 48 / 256;
   switch (prec) {
     case PREC_F64:
+      if (t128 >= 2 * cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x128_K2;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     case PREC_F32:
       if (t128 >= 2 * cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x64_K2;
-      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+      return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
     case PREC_BF16:
       if (t128 >= 2 * cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x128_W8;

@@ -110,12 +110,22 @@ template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1> struct Shape {
 };
 
 // K-tile depth of a (precision, shape) pair on the direct-to-LDS path:
-// binary64 tiles of 128 x 128 outputs and more take 32-deep K-tiles (twice
-// the MFMA work per barrier); smaller ones keep 16 so that several
-// workgroups fit in LDS. The register path uses Traits<P>::BK throughout.
+// binary64 tiles of 128 x 128 outputs with 8 waves (one workgroup per CU)
+// take 32-deep K-tiles (twice the MFMA work per barrier); the others keep
+// 16 so that two or more workgroups fit in LDS. binary32 takes 16 unless a
+// 16-deep K-tile of A or B is fewer 1 KiB transfers than the shape has
+// waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32. The register
+// path uses Traits<P>::BK.
 template <int P, class S> __host__ __device__ constexpr int bk_of() {
-  if constexpr (P == PREC_F64) return S::BM * S::BN >= 128 * 128 ? 32 : 16;
-  else return Traits<P>::BK;
+  if constexpr (P == PREC_F64) {
+    return S::BM * S::BN >= 128 * 128 && S::NT >= 512 ? 32 : 16;
+  } else if constexpr (P == PREC_F32) {
+    constexpr int waves = S::NT / 64;
+    constexpr bool even16 = (S::BM * 16 * 4 / 1024) % waves == 0 && (S::BN * 16 * 4 / 1024) % waves == 0;
+    return even16 ? 16 : 32;
+  } else {
+    return Traits<P>::BK;
+  }
 }
 
 // A K split needs every wave's share of a K-tile to hold whole MFMA steps.

@@ -237,11 +237,14 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
   // Ring depth: transfers run NS - 1 K-tiles ahead of the MFMAs. binary64
-  // and binary32: three stages when they fit in 144 KiB of the 160 KiB LDS,
-  // else two. 16-bit: as many stages as fit in the ring budget (2 to 8);
-  // small tiles get deeper rings, large tiles keep several workgroups per
-  // CU. vmcnt (6 bits) bounds the transfers a wave may leave outstanding.
-  static constexpr int FIT = (T::KPL == 8 ? kRing16 : 144 * 1024) / STAGE;
+  // and binary32: three stages when they fit in the ring budget, else two;
+  // the budget is 72 KiB for 4-wave shapes, so that two workgroups share a
+  // CU and one's barrier waits overlap the other's MFMAs (binary64 128 x 128
+  // at N = 4096: 67.4 against 60.1 TFLOP/s with three stages and one
+  // workgroup), and 144 KiB of the 160 KiB LDS for 8-wave shapes. 16-bit: as
+  // many stages as fit in the 16-bit ring budget (2 to 8). vmcnt (6 bits)
+  // bounds the transfers a wave may leave outstanding.
+  static constexpr int FIT = (T::KPL == 8 ? kRing16 : (S::NT <= 256 ? 72 : 144) * 1024) / STAGE;
   static constexpr int VMAX = 1 + 63 / (PER_WAVE > 0 ? PER_WAVE : 1);
   static constexpr int NS0 = T::KPL == 8 ? (FIT < 8 ? FIT : 8) : (FIT >= 3 ? 3 : 2);
   static constexpr int NS1 = NS0 < VMAX ? NS0 : VMAX;
