@@ -32,16 +32,18 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
                                          {64, 64, "64x64"},     {32, 32, "32x32"},
                                          {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
                                          {128, 64, "128x64k2"},   {64, 64, "64x64k2"},
-                                         {32, 32, "32x32k2"}};
+                                         {32, 32, "32x32k2"},     {128, 256, "128x256w8"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
 
 // The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
+// The 128x256w8 shape is 16-bit only.
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
+  if (cfg == CFG_128x256_W8) return prec == PREC_BF16 || prec == PREC_SPLIT;
   return true;
 }
 bool cfg_grouped(int cfg) {
@@ -89,10 +91,11 @@ static int choose_cfg(int prec, int64_t m, int64_t n) {
       if (t128 >= big) return CFG_128x64_K2;
       return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
     case PREC_BF16:
-      if (t128 >= 2 * cus) return CFG_128x128;
+      if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     default:  // split
+      if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
   }

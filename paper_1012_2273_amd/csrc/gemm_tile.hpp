@@ -100,9 +100,10 @@ struct GemmArgs {
 
 // Tile shape: BM x BN outputs per workgroup, WM x WN wave positions (64
 // lanes each), KS waves per position splitting every K-tile between them
-// (their partial sums are added through LDS at the end of the tile).
-template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1> struct Shape {
-  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KS = KS_;
+// (their partial sums are added through LDS at the end of the tile); KB > 0
+// fixes the K-tile depth of the direct-to-LDS path (else bk_of's rule).
+template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1, int KB_ = 0> struct Shape {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KS = KS_, KB = KB_;
   static constexpr int NT = 64 * WM * WN * KS;
   static constexpr int WTM = BM / WM, WTN = BN / WN;   // per-wave tile
   static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 blocks per wave
@@ -114,10 +115,12 @@ template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1> struct Shape {
 // take 32-deep K-tiles (twice the MFMA work per barrier); the others keep
 // 16 so that two or more workgroups fit in LDS. binary32 takes 16 unless a
 // 16-deep K-tile of A or B is fewer 1 KiB transfers than the shape has
-// waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32. The register
-// path uses Traits<P>::BK.
+// waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32. A shape's KB
+// overrides the rule. The register path uses Traits<P>::BK.
 template <int P, class S> __host__ __device__ constexpr int bk_of() {
-  if constexpr (P == PREC_F64) {
+  if constexpr (S::KB > 0) {
+    return S::KB;
+  } else if constexpr (P == PREC_F64) {
     return S::BM * S::BN >= 128 * 128 && S::NT >= 512 ? 32 : 16;
   } else if constexpr (P == PREC_F32) {
     constexpr int waves = S::NT / 64;

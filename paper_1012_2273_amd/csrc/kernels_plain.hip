@@ -76,6 +76,7 @@ using S128x128k2 = Shape<128, 128, 2, 2, 2>;
 using S128x64k2 = Shape<128, 64, 2, 2, 2>;
 using S64x64k2 = Shape<64, 64, 2, 2, 2>;
 using S32x32k2 = Shape<32, 32, 2, 2, 2>;
+using S128x256w8 = Shape<128, 256, 2, 4, 1, 32>;
 
 template <int P>
 static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipStream_t s) {
@@ -89,6 +90,12 @@ static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipSt
     case CFG_128x64_K2: return by_layout<P, S128x64k2>(layout, vec, a, s);
     case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, a, s);
     case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, a, s);
+    case CFG_128x256_W8:
+      if constexpr (P == PREC_BF16 || P == PREC_SPLIT) {
+        return by_layout<P, S128x256w8>(layout, vec, a, s);
+      } else {
+        return hipErrorInvalidValue;   // 16-bit only (the host never picks it)
+      }
   }
   return hipErrorInvalidValue;
 }
