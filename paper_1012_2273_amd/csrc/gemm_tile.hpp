@@ -115,8 +115,10 @@ template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1, int KB_ = 0> struct S
 // take 32-deep K-tiles (twice the MFMA work per barrier); the others keep
 // 16 so that two or more workgroups fit in LDS. binary32 takes 16 unless a
 // 16-deep K-tile of A or B is fewer 1 KiB transfers than the shape has
-// waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32. A shape's KB
-// overrides the rule. The register path uses Traits<P>::BK.
+// waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32, and 32 on the
+// 4-wave 128 x 128 tile (two workgroups of 64 KiB per CU: 131.8 against
+// 124.2 TFLOP/s at N = 4096 with 16-deep K-tiles and three workgroups). A
+// shape's KB overrides the rule. The register path uses Traits<P>::BK.
 template <int P, class S> __host__ __device__ constexpr int bk_of() {
   if constexpr (S::KB > 0) {
     return S::KB;
@@ -125,7 +127,8 @@ template <int P, class S> __host__ __device__ constexpr int bk_of() {
   } else if constexpr (P == PREC_F32) {
     constexpr int waves = S::NT / 64;
     constexpr bool even16 = (S::BM * 16 * 4 / 1024) % waves == 0 && (S::BN * 16 * 4 / 1024) % waves == 0;
-    return even16 ? 16 : 32;
+    constexpr bool big4 = S::NT == 256 && S::BM * S::BN >= 128 * 128;
+    return even16 && !big4 ? 16 : 32;
   } else {
     return Traits<P>::BK;
   }
