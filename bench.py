@@ -16,10 +16,21 @@ seeded synthetic inputs:
 Each path is bracketed by HIP events on torch's current stream (the stream
 the kernels run on); the step loop is bracketed by device synchronisation.
 ``value`` is the binary64 rate 2N^3/t at N = 2000; the split rate and every
-other path are reported beside it with their normwise error against the
-binary64 oracle. ``roofline`` describes the binary64 kernel (MFMA bound);
-``cpu_baseline`` times the oracle (the paper's Algorithm 4 loop on all host
+other path are reported beside it with their normwise error against the host
+binary64 BLAS product of the same inputs (the tests hold every path to the
+oracle; the bench calls the oracle only in its CPU-baseline leg).
+``roofline`` describes the binary64 kernel (MFMA bound); ``cpu_baseline``
+times the oracle (the paper's Algorithm 4 loop on all host
 threads) on the same N = 2000 binary64 product.
+
+Outside the timed step loop (each skippable):
+  sweep     binary64 at the paper's sizes N = 10 ... 2000 plus 4096: median
+            per-call rate (2N^3 and the paper's N^2(2N-1) count), error; for
+            N <= 100 also single-call latency and 1000 back-to-back launches
+  transfer  N = 2000 binary64 with the operands on the host (pinned): H2D of
+            A and B, the product, D2H of C, timed together (never ``value``)
+  host      the host CPU, the single-thread oracle at N = 500 and the
+            Algorithm 4 loop on two threads at N = 2000 (the paper's two cores)
 """
 from __future__ import annotations
 
@@ -75,6 +86,142 @@ def host_threads():
         return os.cpu_count() or 1
 
 
+def _blas(A, B):
+    """Host binary64 BLAS product of the exact inputs: the bench's error
+    reference (the tests hold every path to the oracle itself)."""
+    return np.matmul(np.asarray(A, np.float64), np.asarray(B, np.float64))
+
+
+def _relerr(C, R):
+    d = float(np.linalg.norm((np.asarray(C, np.float64) - R).ravel()))
+    r = float(np.linalg.norm(R.ravel()))
+    return d / r if r > 0 else d
+
+
+def _entries(A, B, r, c):
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    return np.einsum("ij,ji->i", A[r, :], B[:, c])
+
+
+def _median_ms(pairs):
+    return float(np.median([a.elapsed_time(b) for a, b in pairs]))
+
+
+def fp64_sweep(G, torch, dev, stream, inputs, check):
+    """The paper's size sweep (Tables 1-2: N = 100 ... 2000) plus N = 10 and
+    4096, binary64, inputs resident."""
+    out = {}
+    for n in (10, 100, 500, 1000, 2000, 4096):
+        A, B = inputs.uniform_square(n, inputs.seed_for(1, n))
+        Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        Cd = torch.empty((n, n), dtype=torch.float64, device=dev)
+        # warm up for at least 30 ms of back-to-back calls: after the thousands
+        # of tiny launches of the small sizes the clock needs time to come back
+        t_end = time.perf_counter() + 0.03
+        while True:
+            for _ in range(5):
+                G.gemm_plain(Ad, Bd, Cd)
+            torch.cuda.synchronize()
+            if time.perf_counter() >= t_end:
+                break
+        reps = 20 if n >= 1000 else 200
+        pairs = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            G.gemm_plain(Ad, Bd, Cd)
+            e1.record(stream)
+            pairs.append((e0, e1))
+        torch.cuda.synchronize()
+        t = _median_ms(pairs) * 1e-3
+        d = {"ms": round(t * 1e3, 5), "gflops": round(2.0 * n ** 3 / t / 1e9, 2),
+             "gflops_paper_count": round(n * n * (2 * n - 1) / t / 1e9, 2),
+             "frac_peak": round(2.0 * n ** 3 / t / 1e12 / PEAK["f64"], 4)}
+        if n <= 100:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(1000):
+                G.gemm_plain(Ad, Bd, Cd)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            per = e0.elapsed_time(e1) * 1e-3 / 1000
+            d["latency_us"] = round(t * 1e6, 2)
+            d["amortised_us"] = round(per * 1e6, 3)
+            d["amortised_gflops"] = round(2.0 * n ** 3 / per / 1e9, 3)
+            d["amortised_gbs"] = round(24.0 * n * n / per / 1e9, 2)   # A, B, C once
+        if check:
+            C = Cd.cpu().numpy()
+            d["rel_err"] = float(f"{_relerr(C, _blas(A, B)):.3e}")
+        out[str(n)] = d
+        del Ad, Bd, Cd
+    return out
+
+
+def transfer_inclusive(G, torch, dev, stream, A, B, C_resident, reps=10):
+    """N = 2000 binary64 with the operands starting and ending in pinned host
+    memory: H2D of A and B, the product, D2H of C on one stream."""
+    n = A.shape[0]
+    Ah = torch.empty((n, n), dtype=torch.float64, pin_memory=True)
+    Bh = torch.empty((n, n), dtype=torch.float64, pin_memory=True)
+    Ch = torch.empty((n, n), dtype=torch.float64, pin_memory=True)
+    Ah.copy_(torch.from_numpy(A))
+    Bh.copy_(torch.from_numpy(B))
+    Ad = torch.empty((n, n), dtype=torch.float64, device=dev)
+    Bd = torch.empty_like(Ad)
+    Cd = torch.empty_like(Ad)
+    rows = []
+    for i in range(reps + 2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        Ad.copy_(Ah, non_blocking=True)
+        Bd.copy_(Bh, non_blocking=True)
+        ev[1].record(stream)
+        G.gemm_plain(Ad, Bd, Cd)
+        ev[2].record(stream)
+        Ch.copy_(Cd, non_blocking=True)
+        ev[3].record(stream)
+        if i >= 2:
+            rows.append(ev)
+    torch.cuda.synchronize()
+    h2d = float(np.median([e[0].elapsed_time(e[1]) for e in rows]))
+    mm = float(np.median([e[1].elapsed_time(e[2]) for e in rows]))
+    d2h = float(np.median([e[2].elapsed_time(e[3]) for e in rows]))
+    tot = float(np.median([e[0].elapsed_time(e[3]) for e in rows]))
+    return {"N": n, "ms_total": round(tot, 4), "ms_h2d": round(h2d, 4), "ms_product": round(mm, 4),
+            "ms_d2h": round(d2h, 4), "gflops": round(2.0 * n ** 3 / (tot * 1e-3) / 1e9, 2),
+            "h2d_gbs": round(16.0 * n * n / (h2d * 1e-3) / 1e9, 2),
+            "d2h_gbs": round(8.0 * n * n / (d2h * 1e-3) / 1e9, 2),
+            "matches_resident": bool(torch.equal(Ch, C_resident.cpu()))}
+
+
+def host_info(oracle, inputs):
+    """The host CPU, the single-thread oracle at N = 500 and the paper's
+    Algorithm 4 on two threads at N = 2000."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    A, B = inputs.uniform_square(500, inputs.seed_for(0, 500))
+    t0 = time.perf_counter()
+    oracle.gemm(A, B)
+    t1 = time.perf_counter() - t0
+    A, B = inputs.uniform_square(2000, inputs.seed_for(1, 2000))
+    t0 = time.perf_counter()
+    oracle.gemm_omp(A, B, 2)
+    t2 = time.perf_counter() - t0
+    return {"cpu": model, "threads_available": host_threads(),
+            "oracle_1thread_n500": {"s": round(t1, 3), "gflops": round(2.0 * 500 ** 3 / t1 / 1e9, 3)},
+            "alg4_2threads_n2000": {"s": round(t2, 3), "gflops": round(2.0 * 2000 ** 3 / t2 / 1e9, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,9 +230,11 @@ def main():
     ap.add_argument("--paths", default=",".join(ALL_PATHS))
     ap.add_argument("--n", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true", help="skip the oracle error check")
+    ap.add_argument("--no-check", action="store_true", help="skip the error check")
     ap.add_argument("--tile-config", type=int, default=-1,
                     help="force one tile configuration id for single-product launches")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the binary64 size sweep")
+    ap.add_argument("--no-transfer", action="store_true", help="skip the host-buffer timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device-to-device copy of 512 MiB (3 times) so that "
                          "counter runs can scale FETCH_SIZE/WRITE_SIZE to bytes")
@@ -223,31 +372,28 @@ def main():
         del gC
 
     # ---------------------------------------------------------- error check
-    import oracle
+    # against the host binary64 BLAS product of the same inputs
     errs = {}
     if not args.no_check:
         A, B = host["fp64"]
-        t0 = time.time()
-        ref64 = oracle.gemm_omp(A, B)
-        errs["fp64"] = oracle.relerr_fro(C64d.cpu().numpy(), ref64)
-        log(f"oracle fp64 N={N}: {time.time() - t0:.1f}s")
+        errs["fp64"] = _relerr(C64d.cpu().numpy(), _blas(A, B))
         if "f32" in host:
             A, B = host["f32"]
-            ref32 = oracle.gemm_omp(A, B)
+            ref32 = _blas(A, B)
             if "split" in order:
-                errs["split"] = oracle.relerr_fro(Csd.cpu().double().numpy(), ref32)
+                errs["split"] = _relerr(Csd.cpu().double().numpy(), ref32)
             if "fp32" in order:
-                errs["fp32"] = oracle.relerr_fro(C32d.cpu().double().numpy(), ref32)
+                errs["fp32"] = _relerr(C32d.cpu().double().numpy(), ref32)
             if "bf16" in order:
-                errs["bf16"] = oracle.relerr_fro(C16d.cpu().double().numpy(), ref32)
+                errs["bf16"] = _relerr(C16d.cpu().double().numpy(), ref32)
         if "backward" in order:
             Ab, Bb, Wb = host["backward"]
             g = np.random.Generator(np.random.PCG64(1))
             r = g.integers(0, Ab.shape[0], 400)
             c = g.integers(0, Ab.shape[0], 400)
             dA, dB = (t.cpu().double().numpy() for t in bw_out["d"])
-            eA = oracle.relerr_sampled(dA[r, c], oracle.gemm_entries(Wb, np.ascontiguousarray(Bb.T), r, c))
-            eB = oracle.relerr_sampled(dB[r, c], oracle.gemm_entries(np.ascontiguousarray(Ab.T), Wb, r, c))
+            eA = _relerr(dA[r, c], _entries(Wb, Bb.T, r, c))
+            eB = _relerr(dB[r, c], _entries(Ab.T, Wb, r, c))
             errs["backward"] = max(eA, eB)
         if "grouped" in order:
             sizes, gprobs = host["grouped"]
@@ -259,7 +405,7 @@ def main():
                 r = g.integers(0, n, 40)
                 c = g.integers(0, n, 40)
                 got = plan.Cs[i].cpu().numpy()[r, c]
-                worst = max(worst, oracle.relerr_sampled(got, oracle.gemm_entries(A, B, r, c)))
+                worst = max(worst, _relerr(got, _entries(A, B, r, c)))
             errs["grouped"] = worst
 
     # ---------------------------------------------------------- cpu baseline
@@ -268,14 +414,30 @@ def main():
         import oracle
         thr = host_threads()
         A, B = host["fp64"]
-        t0 = time.perf_counter()
-        oracle.gemm_omp(A, B, thr)
-        tc = time.perf_counter() - t0
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.gemm_omp(A, B, thr)
+            runs.append(time.perf_counter() - t0)
+        tc = float(np.median(runs))
         cpu = {"value": round(2.0 * N ** 3 / tc / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
                "kind": "oracle",
                "sample": f"the full N={N} binary64 product, oracle loop (row, column, "
                          f"reduction; no FMA) with rows split statically over {thr} threads "
-                         f"as in the paper's Algorithm 4; {tc:.2f} s"}
+                         f"as in the paper's Algorithm 4; median of 3 runs, {tc:.2f} s each"}
+
+    # ------------------------------------------- outside the timed step loop
+    sweep = None
+    if not args.no_sweep:
+        sweep = fp64_sweep(G, torch, dev, stream, inputs, not args.no_check)
+    xfer = None
+    if not args.no_transfer:
+        A, B = host["fp64"]
+        xfer = transfer_inclusive(G, torch, dev, stream, A, B, C64d)
+    hinfo = None
+    if not args.no_cpu_baseline:
+        import oracle     # the CPU-baseline leg: the oracle timed on the host
+        hinfo = host_info(oracle, inputs)
 
     # ---------------------------------------------------------- report
     paths_out = {}
@@ -318,11 +480,15 @@ def main():
                        "vs_fp64": (round(ms["fp64"] / ms["split"], 2)
                                  if "split" in ms and "fp64" in ms else None)},
         "fp64_rel_err": paths_out.get("fp64", {}).get("rel_err"),
+        "rel_err_reference": "normwise, against the host binary64 BLAS product of the same inputs",
         "paths": paths_out,
         "roofline": ({"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
                       "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),
                       "traffic": traffic} if "fp64" in ms else None),
         "cpu_baseline": cpu,
+        "sweep_fp64": sweep,
+        "transfer_inclusive": xfer,
+        "host": hinfo,
     }
     print(json.dumps(line), flush=True)
     if plan is not None:
