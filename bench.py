@@ -26,7 +26,8 @@ threads) on the same N = 2000 binary64 product.
 Outside the timed step loop (each skippable):
   sweep     binary64 at the paper's sizes N = 10 ... 2000 plus 4096: median
             per-call rate (2N^3 and the paper's N^2(2N-1) count), error; for
-            N <= 100 also single-call latency and 1000 back-to-back launches
+            N <= 100 also single-call latency and 1000 back-to-back launches;
+            and six rectangular binary64 shapes (m x k times k x n)
   transfer  N = 2000 binary64 with the operands on the host (pinned): H2D of
             A and B, the product, D2H of C, timed together (never ``value``)
   host      the host CPU, the single-thread oracle at N = 500 and the
@@ -156,6 +157,44 @@ def fp64_sweep(G, torch, dev, stream, inputs, check):
             C = Cd.cpu().numpy()
             d["rel_err"] = float(f"{_relerr(C, _blas(A, B)):.3e}")
         out[str(n)] = d
+        del Ad, Bd, Cd
+    return out
+
+
+RECT_SHAPES = [(2000, 1000, 3000), (3000, 3000, 3000), (8192, 512, 8192), (512, 8192, 8192),
+               (4096, 4096, 512), (256, 256, 65536)]
+
+
+def rect_sweep(G, torch, dev, stream, inputs, check):
+    """Rectangular binary64 products (m x k times k x n, the paper's problem
+    statement), median per-call rate after >= 30 ms of warm-up."""
+    out = {}
+    for m, n, k in RECT_SHAPES:
+        A, B = inputs.uniform_mnk(m, n, k, 5_000_000 + m + n + k)
+        Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        Cd = torch.empty((m, n), dtype=torch.float64, device=dev)
+        t_end = time.perf_counter() + 0.03
+        while True:
+            for _ in range(3):
+                G.gemm_plain(Ad, Bd, Cd)
+            torch.cuda.synchronize()
+            if time.perf_counter() >= t_end:
+                break
+        pairs = []
+        for _ in range(10):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            G.gemm_plain(Ad, Bd, Cd)
+            e1.record(stream)
+            pairs.append((e0, e1))
+        torch.cuda.synchronize()
+        t = _median_ms(pairs) * 1e-3
+        d = {"ms": round(t * 1e3, 5), "gflops": round(2.0 * m * n * k / t / 1e9, 2),
+             "frac_peak": round(2.0 * m * n * k / t / 1e12 / PEAK["f64"], 4)}
+        if check:
+            d["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), _blas(A, B)):.3e}")
+        out[f"{m}x{n}x{k}"] = d
         del Ad, Bd, Cd
     return out
 
@@ -427,9 +466,10 @@ def main():
                          f"as in the paper's Algorithm 4; median of 3 runs, {tc:.2f} s each"}
 
     # ------------------------------------------- outside the timed step loop
-    sweep = None
+    sweep = rect = None
     if not args.no_sweep:
         sweep = fp64_sweep(G, torch, dev, stream, inputs, not args.no_check)
+        rect = rect_sweep(G, torch, dev, stream, inputs, not args.no_check)
     xfer = None
     if not args.no_transfer:
         A, B = host["fp64"]
@@ -487,6 +527,7 @@ def main():
                       "traffic": traffic} if "fp64" in ms else None),
         "cpu_baseline": cpu,
         "sweep_fp64": sweep,
+        "sweep_rect_fp64": rect,
         "transfer_inclusive": xfer,
         "host": hinfo,
     }

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -72,12 +73,12 @@ static int device_cus() {
 // products N = 500 .. 8192, every shape forced in turn). The deciding
 // quantity is how many 128 x 128 tiles C has against the 256 CUs: with
 // fewer than ~48 smaller tiles are needed to occupy the CUs, up to ~200 the
-// medium shapes win, above that the two-waves-per-SIMD shapes (K split for
-// binary64, 8 waves for the split product) or the 128 x 64 shape (bf16,
-// whose 16-bit MFMAs need more resident waves to hide LDS latency).
-static int choose_cfg(int prec, int64_t m, int64_t n) {
-  const int forced = g_force_cfg.load();
-  if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced)) return forced;
+// medium shapes win, above that one 8-wave workgroup per CU (K split for
+// binary64, 128 x 64 K split for binary32, 8 waves for the 16-bit paths),
+// and from two tiles per CU on the shapes that keep two or more
+// workgroups per CU (4-wave 128 x 128 for binary64/binary32) or move fewer
+// operand bytes per flop (128 x 256 for the 16-bit paths).
+static int choose_rule(int prec, int64_t m, int64_t n) {
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
   const int64_t cus = device_cus();
   const int64_t big = cus * 200 / 256, mid = cus * 48 / 256;
@@ -99,6 +100,69 @@ static int choose_cfg(int prec, int64_t m, int64_t n) {
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
   }
+}
+
+// Workgroups one CU holds for a kernel, cached per device.
+static int occupancy(int prec, int layout, int cfg, bool vec) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  const auto key = std::make_tuple(dev, prec, layout, cfg, vec ? 1 : 0);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int occ = plain_occupancy(prec, layout, cfg, vec);
+  if (occ <= 0) occ = 1;
+  cache[key] = occ;
+  return occ;
+}
+
+// Large-N rate (TFLOP/s, square NN products N = 4096-8192 on MI355X) of the
+// binary64/binary32 shapes the round-count check compares.
+static double shape_rate(int prec, int cfg) {
+  if (prec == PREC_F64) {
+    switch (cfg) {
+      case CFG_128x128: return 67.4;
+      case CFG_128x128_K2: return 65.6;
+      case CFG_64x64: return 61.3;
+    }
+  } else {
+    switch (cfg) {
+      case CFG_128x128: return 134.0;
+      case CFG_128x64_K2: return 127.0;
+      case CFG_64x64_K2: return 119.6;
+    }
+  }
+  return 0.0;
+}
+
+// Time estimate of a shape in whole rounds of the device's workgroup slots:
+// rounds x (tiles a CU holds per round x tile area) / large-N rate.
+static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int64_t n) {
+  const int bm = kCfgs[cfg].bm, bn = kCfgs[cfg].bn;
+  const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
+  const int occ = occupancy(prec, layout, cfg, vec);
+  const int64_t slots = (int64_t)device_cus() * occ;
+  const int64_t rounds = (tiles + slots - 1) / slots;
+  return (double)rounds * occ * bm * bn / shape_rate(prec, cfg);
+}
+
+// The rule above ignores how full the last round of workgroups is: at
+// N = 3000 binary64, 576 tiles of 128 x 128 take two rounds of 512 slots
+// (46 TFLOP/s) where 2209 tiles of 64 x 64 fill three rounds of 768 (57).
+// binary64/binary32 step down to the 64 x 64 shape when the round count
+// says it is at least 15% faster.
+static int choose_cfg(int prec, int layout, bool vec, int64_t m, int64_t n) {
+  const int forced = g_force_cfg.load();
+  if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced)) return forced;
+  const int pick = choose_rule(prec, m, n);
+  if (prec != PREC_F64 && prec != PREC_F32) return pick;
+  const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
+  if (kCfgs[pick].bm < 128 || shape_rate(prec, pick) <= 0.0) return pick;
+  const double cp = round_cost(prec, layout, vec, pick, m, n);
+  const double ca = round_cost(prec, layout, vec, alt, m, n);
+  return ca < 0.85 * cp ? alt : pick;
 }
 
 static size_t esize_of(int dtype) {
@@ -147,10 +211,10 @@ static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hi
   int rc;
   if ((rc = check_ld_range("A", a.lda, es_in)) || (rc = check_ld_range("B", a.ldb, es_in)))
     return rc;
-  const int cfg = choose_cfg(prec, a.M, a.N);
   const bool ta = layout == LAYOUT_TN, tb = layout == LAYOUT_NT;
   bool vec = vec_ok(a.A, a.lda, es_in, ta ? a.M : a.K) && vec_ok(a.B, a.ldb, es_in, tb ? a.K : a.N);
   if (prec == PREC_SPLIT) vec = true;   // planes are padded to whole vectors
+  const int cfg = choose_cfg(prec, layout, vec, a.M, a.N);
   hipError_t e = launch_plain(prec, layout, cfg, vec, a, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return GEMM_OK;

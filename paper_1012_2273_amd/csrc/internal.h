@@ -37,6 +37,8 @@ enum Layout : int { LAYOUT_NN = 0, LAYOUT_NT = 1, LAYOUT_TN = 2 };
 // prec: 0 f64, 1 f32, 2 bf16, 3 split. Returns hipSuccess or the launch error.
 hipError_t launch_plain(int prec, int layout, int cfg, bool vec, const GemmArgs &a,
                         hipStream_t stream);
+// Workgroups of that kernel one CU holds at once (0 if not offered or unknown).
+int plain_occupancy(int prec, int layout, int cfg, bool vec);
 
 // Split kernels: X (rows x cols, ldx) -> hi/lo 16-bit planes. Plane rows
 // are written up to `out_pad` >= their length (cols, or rows when

@@ -44,26 +44,38 @@ static hipError_t launch_one(const GemmArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int P, class S, bool TA, bool TB>
-static hipError_t by_vec(bool vec, const GemmArgs &a, hipStream_t s) {
-  return vec ? launch_one<P, S, TA, TB, true>(a, s) : launch_one<P, S, TA, TB, false>(a, s);
+// One instantiation of the single-product kernel pair (precision, shape,
+// operand layout, vector path), handed to a visitor.
+template <int P, class S, bool TA, bool TB, bool VEC> struct KTag {};
+
+template <int P, class S, bool TA, bool TB, bool VEC> static int occupancy_one() {
+  int per = 0;
+  hipError_t e;
+  if constexpr (VEC && dma_ok<P, S, TA, TB>())
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_plain_dma_kernel<P, S, TA, TB>, S::NT, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_plain_kernel<P, S, TA, TB, VEC>, S::NT, 0);
+  return e == hipSuccess ? per : 0;
 }
 
-template <int P, class S>
-static hipError_t by_layout(int layout, bool vec, const GemmArgs &a, hipStream_t s) {
+// Visitors return an int >= 0, or -1 for a combination that is not offered.
+template <int P, class S, class F> static int by_layout(int layout, bool vec, F &f) {
   if constexpr (!shape_ok<P, S>()) {
-    return hipErrorInvalidValue;   // not offered for this precision (the host never picks it)
+    return -1;   // not offered for this precision (the host never picks it)
   } else if constexpr (P == PREC_SPLIT) {
     // the split planes are always written K-contiguous and 16-byte aligned
-    if (layout != LAYOUT_NT || !vec) return hipErrorInvalidValue;
-    return launch_one<P, S, false, true, true>(a, s);
+    if (layout != LAYOUT_NT || !vec) return -1;
+    return f(KTag<P, S, false, true, true>{});
   } else {
     switch (layout) {
-      case LAYOUT_NN: return by_vec<P, S, false, false>(vec, a, s);
-      case LAYOUT_NT: return by_vec<P, S, false, true>(vec, a, s);
-      case LAYOUT_TN: return by_vec<P, S, true, false>(vec, a, s);
+      case LAYOUT_NN:
+        return vec ? f(KTag<P, S, false, false, true>{}) : f(KTag<P, S, false, false, false>{});
+      case LAYOUT_NT:
+        return vec ? f(KTag<P, S, false, true, true>{}) : f(KTag<P, S, false, true, false>{});
+      case LAYOUT_TN:
+        return vec ? f(KTag<P, S, true, false, true>{}) : f(KTag<P, S, true, false, false>{});
     }
-    return hipErrorInvalidValue;
+    return -1;
   }
 }
 
@@ -78,37 +90,51 @@ using S64x64k2 = Shape<64, 64, 2, 2, 2>;
 using S32x32k2 = Shape<32, 32, 2, 2, 2>;
 using S128x256w8 = Shape<128, 256, 2, 4, 1, 32>;
 
-template <int P>
-static hipError_t by_cfg(int layout, int cfg, bool vec, const GemmArgs &a, hipStream_t s) {
+template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f) {
   switch (cfg) {
-    case CFG_128x128: return by_layout<P, S128x128>(layout, vec, a, s);
-    case CFG_128x64: return by_layout<P, S128x64>(layout, vec, a, s);
-    case CFG_64x64: return by_layout<P, S64x64>(layout, vec, a, s);
-    case CFG_32x32: return by_layout<P, S32x32>(layout, vec, a, s);
-    case CFG_128x128_W8: return by_layout<P, S128x128w8>(layout, vec, a, s);
-    case CFG_128x128_K2: return by_layout<P, S128x128k2>(layout, vec, a, s);
-    case CFG_128x64_K2: return by_layout<P, S128x64k2>(layout, vec, a, s);
-    case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, a, s);
-    case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, a, s);
+    case CFG_128x128: return by_layout<P, S128x128>(layout, vec, f);
+    case CFG_128x64: return by_layout<P, S128x64>(layout, vec, f);
+    case CFG_64x64: return by_layout<P, S64x64>(layout, vec, f);
+    case CFG_32x32: return by_layout<P, S32x32>(layout, vec, f);
+    case CFG_128x128_W8: return by_layout<P, S128x128w8>(layout, vec, f);
+    case CFG_128x128_K2: return by_layout<P, S128x128k2>(layout, vec, f);
+    case CFG_128x64_K2: return by_layout<P, S128x64k2>(layout, vec, f);
+    case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, f);
+    case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, f);
     case CFG_128x256_W8:
-      if constexpr (P == PREC_BF16 || P == PREC_SPLIT) {
-        return by_layout<P, S128x256w8>(layout, vec, a, s);
-      } else {
-        return hipErrorInvalidValue;   // 16-bit only (the host never picks it)
-      }
+      if constexpr (P == PREC_BF16 || P == PREC_SPLIT)
+        return by_layout<P, S128x256w8>(layout, vec, f);
+      else
+        return -1;   // 16-bit only (the host never picks it)
   }
-  return hipErrorInvalidValue;
+  return -1;
+}
+
+template <class F> static int visit(int prec, int layout, int cfg, bool vec, F &f) {
+  switch (prec) {
+    case PREC_F64: return by_cfg<PREC_F64>(layout, cfg, vec, f);
+    case PREC_F32: return by_cfg<PREC_F32>(layout, cfg, vec, f);
+    case PREC_BF16: return by_cfg<PREC_BF16>(layout, cfg, vec, f);
+    case PREC_SPLIT: return by_cfg<PREC_SPLIT>(layout, cfg, vec, f);
+  }
+  return -1;
 }
 
 hipError_t launch_plain(int prec, int layout, int cfg, bool vec, const GemmArgs &a,
                         hipStream_t stream) {
-  switch (prec) {
-    case PREC_F64: return by_cfg<PREC_F64>(layout, cfg, vec, a, stream);
-    case PREC_F32: return by_cfg<PREC_F32>(layout, cfg, vec, a, stream);
-    case PREC_BF16: return by_cfg<PREC_BF16>(layout, cfg, vec, a, stream);
-    case PREC_SPLIT: return by_cfg<PREC_SPLIT>(layout, cfg, vec, a, stream);
-  }
-  return hipErrorInvalidValue;
+  auto f = [&]<int P, class S, bool TA, bool TB, bool VEC>(KTag<P, S, TA, TB, VEC>) -> int {
+    return (int)launch_one<P, S, TA, TB, VEC>(a, stream);
+  };
+  const int r = visit(prec, layout, cfg, vec, f);
+  return r < 0 ? hipErrorInvalidValue : (hipError_t)r;
+}
+
+int plain_occupancy(int prec, int layout, int cfg, bool vec) {
+  auto f = []<int P, class S, bool TA, bool TB, bool VEC>(KTag<P, S, TA, TB, VEC>) -> int {
+    return occupancy_one<P, S, TA, TB, VEC>();
+  };
+  const int r = visit(prec, layout, cfg, vec, f);
+  return r < 0 ? 0 : r;
 }
 
 }  // namespace g355
