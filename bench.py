@@ -6,6 +6,7 @@ A step is one pass over every compute row of the hot path on resident,
 seeded synthetic inputs:
   fp64     gemm_plain binary64, N = 2000, U[-1,1]                 (headline)
   split    gemm_split (split kernels + 3-term bfloat16 product), N = 2000
+  split3   gemm_split3 (three-way split, 6-term bfloat16 product), N = 2000
   fp32     gemm_plain binary32, N = 2000
   bf16     gemm_plain bfloat16 inputs, binary32 output, N = 2000
   backward gemm_backward binary32 (dA and dB), N = 2048, dC = W
@@ -50,7 +51,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # TFLOP/s, dense MFMA
 HBM_PEAK = 8000.0                                    # GB/s
 METRIC = "GFLOP/s (2N^3/t) at N=2000 FP64 vs split-BF16, at stated rel. error"
-ALL_PATHS = ["fp64", "split", "fp32", "bf16", "backward", "grouped"]
+ALL_PATHS = ["fp64", "split", "split3", "fp32", "bf16", "backward", "grouped"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp64_n2000.json")
 # the binary64 kernel's code and the host choice of its tile shape
 KERNEL_SOURCES = ["paper_1012_2273_amd/csrc/gemm_tile.hpp",
@@ -313,13 +314,16 @@ def main():
     C64d = torch.empty((N, N), dtype=torch.float64, device=dev)
     work["fp64"] = (lambda: G.gemm_plain(A64d, B64d, C64d), 2.0 * N ** 3)
 
-    if any(p in paths for p in ("split", "fp32", "bf16")):
+    if any(p in paths for p in ("split", "split3", "fp32", "bf16")):
         A32, B32 = inputs.uniform_square(N, inputs.seed_for(2, N), dtype=np.float32)
         host["f32"] = (A32, B32)
         A32d, B32d = torch.from_numpy(A32).to(dev), torch.from_numpy(B32).to(dev)
         Csd = torch.empty((N, N), dtype=torch.float32, device=dev)
         ws = torch.empty(G.gemm_split_workspace_size(N, N, N), dtype=torch.uint8, device=dev)
         work["split"] = (lambda: G.gemm_split(A32d, B32d, Csd, ws), 2.0 * N ** 3)
+        C3d = torch.empty((N, N), dtype=torch.float32, device=dev)
+        ws3 = torch.empty(G.gemm_split3_workspace_size(N, N, N), dtype=torch.uint8, device=dev)
+        work["split3"] = (lambda: G.gemm_split3(A32d, B32d, C3d, ws3), 2.0 * N ** 3)
         C32d = torch.empty((N, N), dtype=torch.float32, device=dev)
         work["fp32"] = (lambda: G.gemm_plain(A32d, B32d, C32d), 2.0 * N ** 3)
         A16d, B16d = A32d.to(torch.bfloat16), B32d.to(torch.bfloat16)
@@ -421,6 +425,8 @@ def main():
             ref32 = _blas(A, B)
             if "split" in order:
                 errs["split"] = _relerr(Csd.cpu().double().numpy(), ref32)
+            if "split3" in order:
+                errs["split3"] = _relerr(C3d.cpu().double().numpy(), ref32)
             if "fp32" in order:
                 errs["fp32"] = _relerr(C32d.cpu().double().numpy(), ref32)
             if "bf16" in order:

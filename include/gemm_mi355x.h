@@ -114,6 +114,44 @@ int gemm_split(int64_t m, int64_t n, int64_t k,
                void *stream);
 
 /*
+ * gemm_split3_workspace_size -- bytes of device workspace gemm_split3 needs
+ * (six bfloat16 planes laid out as for gemm_split). Returns 0 for negative
+ * sizes.
+ */
+size_t gemm_split3_workspace_size(int64_t m, int64_t n, int64_t k);
+
+/*
+ * gemm_split3_convert -- the three-way split step alone: each binary32
+ * element x becomes hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi -
+ * mid), each rounded to nearest, ties to even; every difference is exact
+ * in binary32, so hi + mid + lo carries all 24 significand bits of a
+ * normal x. Layout, ownership and errors as gemm_split_convert, with three
+ * output planes (hi, mid, lo).
+ */
+int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                        int transpose, uint16_t *hi, uint16_t *mid, uint16_t *lo,
+                        int64_t ldo, void *stream);
+
+/*
+ * gemm_split3 -- C(m x n) ~= A(m x k) * B(k x n) for binary32 A, B, C through
+ * a three-way bfloat16 split of both operands and six products accumulated
+ * in binary32 on the matrix cores, smallest first:
+ *   C = A_lo*B_hi + A_hi*B_lo + A_mid*B_mid + A_mid*B_hi + A_hi*B_mid + A_hi*B_hi
+ * (A_mid*B_lo, A_lo*B_mid and A_lo*B_lo are dropped: together at most about
+ * 2^-23 of |A||B|, below the binary32 accumulation error). The same product
+ * as gemm_plain (Section 3.1, Algorithm 1) at binary32 accuracy, on the
+ * bfloat16 matrix cores; the higher-accuracy variant of gemm_split.
+ *   workspace  device memory of at least gemm_split3_workspace_size(m, n, k)
+ *              bytes, owned by the caller, 16-byte aligned, not shared by
+ *              overlapping calls.
+ * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
+ */
+int gemm_split3(int64_t m, int64_t n, int64_t k,
+                const float *A, int64_t lda, const float *B, int64_t ldb,
+                float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                void *stream);
+
+/*
  * gemm_backward -- gradients of a scalar loss through C = A*B, given
  * dC = dL/dC (m x n):  dA = dC * B^T  (m x k),  dB = A^T * dC  (k x n).
  * The transposed operands are read in place (no transposed copy is made).

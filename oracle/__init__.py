@@ -13,7 +13,8 @@ Source: Hasta and Mutiara, arXiv 1012.2273.
     ``flops_2n3``; Algorithm 2 / Algorithm 4 (rate = ops / t / 1e6).
   * Section 3.1.1, Algorithm 2 (averow / extra / offset row split): ``row_partition``.
 The extensions that the paper does not contain (binary32 and bfloat16
-inputs, the two-term bfloat16 split, batching, the backward product) are
+inputs, the two- and three-term bfloat16 splits, batching, the backward
+product) are
 reduced here to the same binary64 definition applied to the exact values the
 GPU receives, see the individual docstrings.
 """
@@ -60,6 +61,8 @@ def _load():
             lib.oracle_gemm_entries_f64.restype = None
             lib.oracle_split_bf16.argtypes = [i64, fp, dp, dp]
             lib.oracle_split_bf16.restype = None
+            lib.oracle_split3_bf16.argtypes = [i64, fp, dp, dp, dp]
+            lib.oracle_split3_bf16.restype = None
             lib.oracle_bf16_rne_array.argtypes = [i64, fp, dp]
             lib.oracle_bf16_rne_array.restype = None
             lib.oracle_max_threads.argtypes = []
@@ -172,6 +175,30 @@ def split_emul_gemm(A, B) -> np.ndarray:
     ahi, alo = (bf16_to_f32(p) for p in split_bf16(A))
     bhi, blo = (bf16_to_f32(p) for p in split_bf16(B))
     return gemm(ahi, bhi) + gemm(ahi, blo) + gemm(alo, bhi)
+
+
+def split3_bf16(x):
+    """Three-term split: hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi -
+    mid). Returns uint16 planes."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = np.empty(x.shape, dtype=np.uint16)
+    mid = np.empty(x.shape, dtype=np.uint16)
+    lo = np.empty(x.shape, dtype=np.uint16)
+    _load().oracle_split3_bf16(x.size, _ptr(x), _ptr(hi), _ptr(mid), _ptr(lo))
+    return hi, mid, lo
+
+
+def split3_emul_gemm(A, B) -> np.ndarray:
+    """What the six-term split product computes, with exact binary64 sums.
+
+    A_lo*B_hi + A_hi*B_lo + A_mid*B_mid + A_mid*B_hi + A_hi*B_mid + A_hi*B_hi
+    (mid*lo, lo*mid and lo*lo dropped), each term this module's binary64
+    product of bfloat16-valued operands.
+    """
+    ahi, amid, alo = (bf16_to_f32(p) for p in split3_bf16(A))
+    bhi, bmid, blo = (bf16_to_f32(p) for p in split3_bf16(B))
+    return (gemm(alo, bhi) + gemm(ahi, blo) + gemm(amid, bmid) + gemm(amid, bhi)
+            + gemm(ahi, bmid) + gemm(ahi, bhi))
 
 
 # ------------------------------------------------------------- backward

@@ -156,6 +156,27 @@ void oracle_split_bf16(int64_t count, const float *x, uint16_t *hi, uint16_t *lo
     }
 }
 
+/*
+ * Three-term bfloat16 split of binary32 data: hi = bf16(x), mid = bf16(x - hi),
+ * lo = bf16(x - hi - mid). Each difference is computed in binary64, where it
+ * is exact; it is also exactly representable in binary32 (x with its leading
+ * significand bits removed: the second difference is of two binary32 values
+ * within a factor two of each other), so the narrowing casts are exact.
+ */
+void oracle_split3_bf16(int64_t count, const float *x, uint16_t *hi, uint16_t *mid,
+                        uint16_t *lo)
+{
+    for (int64_t t = 0; t < count; ++t) {
+        uint16_t h = oracle_bf16_rne(x[t]);
+        double r1 = (double)x[t] - (double)bf16_bits_to_float(h);
+        uint16_t m = oracle_bf16_rne((float)r1);
+        double r2 = r1 - (double)bf16_bits_to_float(m);
+        hi[t] = h;
+        mid[t] = m;
+        lo[t] = oracle_bf16_rne((float)r2);
+    }
+}
+
 /* Batch form of oracle_bf16_rne. */
 void oracle_bf16_rne_array(int64_t count, const float *x, uint16_t *out)
 {

@@ -96,49 +96,70 @@ def gemm_split_workspace_size(m, n, k) -> int:
     return int(_lib.load().gemm_split_workspace_size(int(m), int(n), int(k)))
 
 
-def gemm_split(A, B, C=None, workspace=None):
-    """float32 C ~= A @ B via the two-way bfloat16 split of A and B and three
-    bfloat16 products accumulated in float32."""
+def gemm_split3_workspace_size(m, n, k) -> int:
+    return int(_lib.load().gemm_split3_workspace_size(int(m), int(n), int(k)))
+
+
+def _split_product(name, size_fn, A, B, C, workspace):
     torch = _torch()
     if A.dtype != torch.float32 or B.dtype != torch.float32:
-        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, "gemm_split", "float32 inputs required")
+        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, name, "float32 inputs required")
     m, k = A.shape
     k2, n = B.shape
     if k2 != k:
-        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_split", "shape mismatch")
+        raise GemmArgError(_lib.GEMM_EINVAL, name, "shape mismatch")
     if C is None:
         C = torch.empty((m, n), dtype=torch.float32, device=A.device)
-    need = gemm_split_workspace_size(m, n, k)
+    need = size_fn(m, n, k)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
     lib = _lib.load()
-    _lib.check(lib.gemm_split(m, n, k, pa, lda, pb, ldb, pc, ldc,
-                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                              _stream(A)), "gemm_split")
+    _lib.check(getattr(lib, name)(m, n, k, pa, lda, pb, ldb, pc, ldc,
+                                  ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                  _stream(A)), name)
     return C
+
+
+def gemm_split(A, B, C=None, workspace=None):
+    """float32 C ~= A @ B via the two-way bfloat16 split of A and B and three
+    bfloat16 products accumulated in float32."""
+    return _split_product("gemm_split", gemm_split_workspace_size, A, B, C, workspace)
+
+
+def gemm_split3(A, B, C=None, workspace=None):
+    """float32 C ~= A @ B via the three-way bfloat16 split of A and B and six
+    bfloat16 products accumulated in float32 (binary32 accuracy)."""
+    return _split_product("gemm_split3", gemm_split3_workspace_size, A, B, C, workspace)
+
+
+def _split_convert(name, planes, X, transpose):
+    torch = _torch()
+    if X.dtype != torch.float32:
+        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, name, "float32 input required")
+    r, c = X.shape
+    shape = (c, r) if transpose else (r, c)
+    outs = [torch.empty(shape, dtype=torch.int16, device=X.device) for _ in range(planes)]
+    px, ldx = _mat(X, "X")
+    ldo = shape[1] if shape[1] > 0 else 1
+    lib = _lib.load()
+    ptrs = [ctypes.c_void_p(t.data_ptr() if t.numel() else 0) for t in outs]
+    _lib.check(getattr(lib, name)(r, c, px, ldx, int(bool(transpose)), *ptrs, ldo, _stream(X)), name)
+    return tuple(outs)
 
 
 def gemm_split_convert(X, transpose=False):
     """(hi, lo) int16 tensors holding the bfloat16 patterns of X's split;
     shape X.shape, or transposed when ``transpose``."""
-    torch = _torch()
-    if X.dtype != torch.float32:
-        raise GemmArgError(_lib.GEMM_EUNSUPPORTED, "gemm_split_convert", "float32 input required")
-    r, c = X.shape
-    shape = (c, r) if transpose else (r, c)
-    hi = torch.empty(shape, dtype=torch.int16, device=X.device)
-    lo = torch.empty(shape, dtype=torch.int16, device=X.device)
-    px, ldx = _mat(X, "X")
-    ldo = shape[1] if shape[1] > 0 else 1
-    lib = _lib.load()
-    _lib.check(lib.gemm_split_convert(r, c, px, ldx, int(bool(transpose)),
-                                      ctypes.c_void_p(hi.data_ptr() if hi.numel() else 0),
-                                      ctypes.c_void_p(lo.data_ptr() if lo.numel() else 0),
-                                      ldo, _stream(X)), "gemm_split_convert")
-    return hi, lo
+    return _split_convert("gemm_split_convert", 2, X, transpose)
+
+
+def gemm_split3_convert(X, transpose=False):
+    """(hi, mid, lo) int16 tensors holding the bfloat16 patterns of X's
+    three-way split; shape X.shape, or transposed when ``transpose``."""
+    return _split_convert("gemm_split3_convert", 3, X, transpose)
 
 
 def gemm_backward(A, B, dC, need_dA=True, need_dB=True):

@@ -44,7 +44,7 @@ static std::atomic<int> g_force_cfg{-1};
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
-  if (cfg == CFG_128x256_W8) return prec == PREC_BF16 || prec == PREC_SPLIT;
+  if (cfg == CFG_128x256_W8) return prec == PREC_BF16 || prec == PREC_SPLIT || prec == PREC_SPLIT3;
   return true;
 }
 bool cfg_grouped(int cfg) {
@@ -95,7 +95,7 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
       if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
-    default:  // split
+    default:  // split, two or three planes
       if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
@@ -213,7 +213,7 @@ static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hi
     return rc;
   const bool ta = layout == LAYOUT_TN, tb = layout == LAYOUT_NT;
   bool vec = vec_ok(a.A, a.lda, es_in, ta ? a.M : a.K) && vec_ok(a.B, a.ldb, es_in, tb ? a.K : a.N);
-  if (prec == PREC_SPLIT) vec = true;   // planes are padded to whole vectors
+  if (prec == PREC_SPLIT || prec == PREC_SPLIT3) vec = true;   // planes are padded to whole vectors
   const int cfg = choose_cfg(prec, layout, vec, a.M, a.N);
   hipError_t e = launch_plain(prec, layout, cfg, vec, a, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -274,57 +274,81 @@ int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_
 
 static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// Workspace layout: A_hi | A_lo (m x kp) then B_hi | B_lo (n x kp), kp = k
-// rounded up to 8 elements (16 bytes) so every plane row is 16-byte aligned;
-// each plane starts on a 256-byte boundary.
-// Plane rows hold kp = k rounded up to 8 elements (zeros past k) at a pitch
+// Workspace layout: the np planes of A (m rows each), then the np planes of
+// B transposed (n rows each), hi first; each plane starts on a 256-byte
+// boundary. Plane rows hold kp = k rounded up to 8 elements (zeros past k,
+// so every plane row is a whole number of 16-byte vectors) at a pitch
 // of ldp = kp rounded up to 64 elements: every row starts on a 128-byte
 // line, so a 16-byte-per-lane transfer of a K-tile touches whole lines
 // (a 4000-byte pitch at k = 2000 made most K-chunks straddle two lines and
 // cost the product 17% at N = 2000).
-static void split_layout(int64_t m, int64_t n, int64_t k, int64_t &kp, int64_t &ldp,
-                         size_t off[4], size_t &total) {
+static void split_layout(int np, int64_t m, int64_t n, int64_t k, int64_t &kp, int64_t &ldp,
+                         size_t off[6], size_t &total) {
   kp = round_up(k > 0 ? k : 1, 8);
   ldp = round_up(kp, 64);
   const size_t a_bytes = (size_t)round_up(m * ldp * 2, 256);
   const size_t b_bytes = (size_t)round_up(n * ldp * 2, 256);
-  off[0] = 0;
-  off[1] = a_bytes;
-  off[2] = 2 * a_bytes;
-  off[3] = 2 * a_bytes + b_bytes;
-  total = 2 * a_bytes + 2 * b_bytes;
+  // A planes first, then B planes: off[p] = A plane p, off[np + p] = B plane p
+  for (int p = 0; p < np; ++p) {
+    off[p] = p * a_bytes;
+    off[np + p] = np * a_bytes + p * b_bytes;
+  }
+  total = np * (a_bytes + b_bytes);
 }
 
 size_t gemm_split_workspace_size(int64_t m, int64_t n, int64_t k) {
   if (m < 0 || n < 0 || k < 0) return 0;
   int64_t kp, ldp;
-  size_t off[4], total;
-  split_layout(m, n, k, kp, ldp, off, total);
+  size_t off[6], total;
+  split_layout(2, m, n, k, kp, ldp, off, total);
   return total;
 }
 
-int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx, int transpose,
-                       uint16_t *hi, uint16_t *lo, int64_t ldo, void *stream) {
+size_t gemm_split3_workspace_size(int64_t m, int64_t n, int64_t k) {
+  if (m < 0 || n < 0 || k < 0) return 0;
+  int64_t kp, ldp;
+  size_t off[6], total;
+  split_layout(3, m, n, k, kp, ldp, off, total);
+  return total;
+}
+
+static int split_convert(int np, int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                         int transpose, uint16_t *const *planes, int64_t ldo, void *stream) {
   clear_error();
   if (rows < 0 || cols < 0) return set_error(GEMM_EINVAL, "negative size");
   if (transpose != 0 && transpose != 1) return set_error(GEMM_EINVAL, "transpose must be 0 or 1");
   int rc;
   if ((rc = check_mat("X", X, rows, cols, ldx))) return rc;
-  if (rows > 0 && cols > 0 && (hi == nullptr || lo == nullptr))
-    return set_error(GEMM_ENULL, "hi/lo plane is NULL");
+  if (rows > 0 && cols > 0)
+    for (int p = 0; p < np; ++p)
+      if (planes[p] == nullptr) return set_error(GEMM_ENULL, "output plane is NULL");
   const int64_t out_cols = transpose ? rows : cols;
   if (ldo < out_cols) return set_error(GEMM_ELD, "ldo smaller than the plane row length");
   if (rows == 0 || cols == 0) return GEMM_OK;
   if ((rc = check_ld_range("X", ldx, 4))) return rc;
-  hipError_t e = launch_split(rows, cols, X, ldx, transpose != 0, hi, lo, ldo,
+  hipError_t e = launch_split(np, rows, cols, X, ldx, transpose != 0, planes, ldo,
                               transpose ? rows : cols, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "split launch");
   return GEMM_OK;
 }
 
-int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
-               int64_t ldb, float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
-               void *stream) {
+int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx, int transpose,
+                       uint16_t *hi, uint16_t *lo, int64_t ldo, void *stream) {
+  uint16_t *planes[2] = {hi, lo};
+  return split_convert(2, rows, cols, X, ldx, transpose, planes, ldo, stream);
+}
+
+int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx, int transpose,
+                        uint16_t *hi, uint16_t *mid, uint16_t *lo, int64_t ldo, void *stream) {
+  uint16_t *planes[3] = {hi, mid, lo};
+  return split_convert(3, rows, cols, X, ldx, transpose, planes, ldo, stream);
+}
+
+// The split product with np planes per operand: one split launch for both
+// operands into the caller's workspace, then the product of the planes.
+static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                         const float *B, int64_t ldb, float *C, int64_t ldc, void *workspace,
+                         size_t workspace_bytes, void *stream) {
   clear_error();
   if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
   int rc;
@@ -333,8 +357,8 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
     return rc;
   if (m == 0 || n == 0) return GEMM_OK;
   int64_t kp, ldp;
-  size_t off[4], total;
-  split_layout(m, n, k, kp, ldp, off, total);
+  size_t off[6], total;
+  split_layout(np, m, n, k, kp, ldp, off, total);
   if (workspace == nullptr || workspace_bytes < total)
     return set_error(GEMM_EWORKSPACE, "need " + std::to_string(total) + " bytes, got " +
                                           std::to_string(workspace_bytes));
@@ -342,17 +366,32 @@ int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, con
     return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   char *ws = (char *)workspace;
-  uint16_t *ahi = (uint16_t *)(ws + off[0]), *alo = (uint16_t *)(ws + off[1]);
-  uint16_t *bhi = (uint16_t *)(ws + off[2]), *blo = (uint16_t *)(ws + off[3]);
+  uint16_t *ap[3] = {nullptr, nullptr, nullptr}, *bp[3] = {nullptr, nullptr, nullptr};
+  for (int p = 0; p < np; ++p) {
+    ap[p] = (uint16_t *)(ws + off[p]);
+    bp[p] = (uint16_t *)(ws + off[np + p]);
+  }
   if (k > 0) {
     // planes carry zeros in the padding columns [k, kp), so the product may
     // run over kp (a whole number of 8-element vectors) unchanged
     if ((rc = check_ld_range("A", lda, 4)) || (rc = check_ld_range("B", ldb, 4))) return rc;
-    hipError_t e = launch_split_pair(m, n, k, A, lda, B, ldb, ahi, alo, bhi, blo, kp, ldp, s);
+    hipError_t e = launch_split_pair(np, m, n, k, A, lda, B, ldb, ap, bp, kp, ldp, s);
     if (e != hipSuccess) return hip_fail(e, "split launch");
   }
-  GemmArgs a{m, n, k > 0 ? kp : 0, ahi, ldp, bhi, ldp, alo, blo, C, ldc};
-  return run_product(PREC_SPLIT, LAYOUT_NT, a, 2, s);
+  GemmArgs a{m, n, k > 0 ? kp : 0, ap[0], ldp, bp[0], ldp, ap[1], bp[1], C, ldc, ap[2], bp[2]};
+  return run_product(np == 2 ? PREC_SPLIT : PREC_SPLIT3, LAYOUT_NT, a, 2, s);
+}
+
+int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+               int64_t ldb, float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+               void *stream) {
+  return split_product(2, m, n, k, A, lda, B, ldb, C, ldc, workspace, workspace_bytes, stream);
+}
+
+int gemm_split3(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+                int64_t ldb, float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                void *stream) {
+  return split_product(3, m, n, k, A, lda, B, ldb, C, ldc, workspace, workspace_bytes, stream);
 }
 
 int gemm_backward(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,

@@ -40,7 +40,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3 };
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3, PREC_SPLIT3 = 4 };
 
 // Per-precision description of the MFMA used and the element types.
 //   E    element type in global memory and LDS (bf16 kept as 16-bit pattern)
@@ -68,6 +68,30 @@ template <> struct Traits<PREC_SPLIT> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
   static constexpr int KPL = 8, BK = 64, PLANES = 2, GRP = 4;   // hi and lo planes
 };
+template <> struct Traits<PREC_SPLIT3> {
+  using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 32, PLANES = 3, GRP = 4;   // hi, mid and lo planes
+};
+
+// The products of a split precision, as (A plane, B plane) pairs in the
+// order they are accumulated: smallest terms first, so that the large ones
+// are added to an accumulator that already holds the small ones. Plane 0 is
+// hi, 1 lo (two planes) or mid, 2 lo (three planes). Two planes: lo*hi,
+// hi*lo, hi*hi (lo*lo dropped). Three planes: lo*hi, hi*lo, mid*mid,
+// mid*hi, hi*mid, hi*hi (mid*lo, lo*mid, lo*lo dropped).
+template <int PL> struct Terms;
+template <> struct Terms<1> {
+  static constexpr int N = 1;
+  static constexpr int a[1] = {0}, b[1] = {0};
+};
+template <> struct Terms<2> {
+  static constexpr int N = 3;
+  static constexpr int a[3] = {1, 0, 0}, b[3] = {0, 1, 0};
+};
+template <> struct Terms<3> {
+  static constexpr int N = 6;
+  static constexpr int a[6] = {2, 0, 1, 1, 0, 0}, b[6] = {0, 2, 1, 0, 1, 0};
+};
 
 __device__ __forceinline__ void mfma(f64x4 &acc, double a, double b) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
@@ -89,13 +113,15 @@ __device__ __forceinline__ void mfma(f32x16 &acc, u16x8 a, u16x8 b) {
 template <typename T, int V> struct alignas(sizeof(T) * V) VecT { T e[V]; };
 
 // Arguments of one product. For PREC_SPLIT, A/B are the hi planes and
-// A2/B2 the lo planes (same leading dimensions).
+// A2/B2 the lo planes; for PREC_SPLIT3, A/B hi, A2/B2 mid and A3/B3 lo (all
+// planes of an operand share its leading dimension).
 struct GemmArgs {
   int64_t M, N, K;
   const void *A; int64_t lda;
   const void *B; int64_t ldb;
   const void *A2; const void *B2;
   void *C; int64_t ldc;
+  const void *A3 = nullptr; const void *B3 = nullptr;
 };
 
 // Tile shape: BM x BN outputs per workgroup, WM x WN wave positions (64
@@ -287,8 +313,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
   const int lr = lane & 15, lgp = lane >> 4;
 
   E *lds = reinterpret_cast<E *>(smem);
-  const E *Ap[2] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2)};
-  const E *Bp[2] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2)};
+  const E *Ap[3] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2),
+                    reinterpret_cast<const E *>(g.A3)};
+  const E *Bp[3] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2),
+                    reinterpret_cast<const E *>(g.B3)};
 
   Mover<E, S::BM, BK, NT, !TA, VEC> ma[PL];
   Mover<E, S::BN, BK, NT, TB, VEC> mb[PL];
@@ -352,20 +380,17 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
   auto mma_unit = [&](auto buf_tag, auto lo_tag, auto hi_tag) {
     constexpr int b = decltype(buf_tag)::value;
     constexpr int lo = decltype(lo_tag)::value, hi = decltype(hi_tag)::value;
+    using TM = Terms<PL>;
 #pragma unroll
     for (int st = 0; st < SPU; ++st) {
-      if constexpr (PL == 2) {
-        // small cross terms first, then hi*hi, into one accumulator
+      // the terms of a split precision, smallest first, into one accumulator
+#pragma unroll
+      for (int t = 0; t < TM::N; ++t) {
 #pragma unroll
         for (int x = lo; x < hi; ++x)
-          mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][1][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
-#pragma unroll
-        for (int x = lo; x < hi; ++x)
-          mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][1][x % S::FN], st));
+          mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][TM::a[t]][x / S::FN], st),
+               op_of(fb[b][TM::b[t]][x % S::FN], st));
       }
-#pragma unroll
-      for (int x = lo; x < hi; ++x)
-        mfma(acc[x / S::FN][x % S::FN], op_of(fa[b][0][x / S::FN], st), op_of(fb[b][0][x % S::FN], st));
     }
   };
   using I0 = std::integral_constant<int, 0>;

@@ -295,8 +295,10 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   const int wm = wpos % S::WM, wn = wpos / S::WM;
   const int lr = lane % MB, lgp = lane / MB;
 
-  const E *Ap[2] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2)};
-  const E *Bp[2] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2)};
+  const E *Ap[3] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2),
+                    reinterpret_cast<const E *>(g.A3)};
+  const E *Bp[3] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2),
+                    reinterpret_cast<const E *>(g.B3)};
   OA oa;
   OB ob;
   oa.init(g.lda, m0, g.M, wave, lane);
@@ -353,7 +355,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   // MFMAs take about as long as the transfers themselves at the L2 -> CU
   // rate (measured 8-10% faster than spreading).
   constexpr bool BURST = KPL == 8;
-  constexpr int MPB = SPU * (PL == 2 ? 3 : 1);          // MFMAs per block per unit
+  using TM = Terms<PL>;
+  constexpr int MPB = SPU * TM::N;                      // MFMAs per block per unit
   constexpr int NPRE = MPB * ((U - 1) * NB + NB1);       // pre-barrier MFMAs per tile
   struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; bool on; };
   Pending pend;
@@ -399,18 +402,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     constexpr int NX = hi - lo;
     [&]<int... m>(std::integer_sequence<int, m...>) {
       (([&] {
-         constexpr int st = m / ((PL == 2 ? 3 : 1) * NX);
-         constexpr int term = (m / NX) % (PL == 2 ? 3 : 1);   // 0: lo*hi, 1: hi*lo, 2: hi*hi
+         constexpr int st = m / (TM::N * NX);
+         constexpr int term = (m / NX) % TM::N;   // Terms<PL> order, smallest first
          constexpr int x = lo + m % NX;
          if constexpr (SLOT >= 0) maybe_issue(std::integral_constant<int, SLOT + m>{});
-         if constexpr (PL == 2 && term == 0)
-           mfma(acc[x / FN][x % FN], op_of(fa[b][1][x / FN], st), op_of(fb[b][0][x % FN], st));
-         else if constexpr (PL == 2 && term == 1)
-           mfma(acc[x / FN][x % FN], op_of(fa[b][0][x / FN], st), op_of(fb[b][1][x % FN], st));
-         else
-           mfma(acc[x / FN][x % FN], op_of(fa[b][0][x / FN], st), op_of(fb[b][0][x % FN], st));
+         mfma(acc[x / FN][x % FN], op_of(fa[b][TM::a[term]][x / FN], st),
+              op_of(fb[b][TM::b[term]][x % FN], st));
        }()), ...);
-    }(std::make_integer_sequence<int, SPU * (PL == 2 ? 3 : 1) * NX>{});
+    }(std::make_integer_sequence<int, SPU * TM::N * NX>{});
   };
   using I0 = std::integral_constant<int, 0>;
   using INB1 = std::integral_constant<int, NB1>;

@@ -40,20 +40,19 @@ hipError_t launch_plain(int prec, int layout, int cfg, bool vec, const GemmArgs 
 // Workgroups of that kernel one CU holds at once (0 if not offered or unknown).
 int plain_occupancy(int prec, int layout, int cfg, bool vec);
 
-// Split kernels: X (rows x cols, ldx) -> hi/lo 16-bit planes. Plane rows
-// are written up to `out_pad` >= their length (cols, or rows when
-// transposed), the padding with zeros.
-hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, bool transpose,
-                        uint16_t *hi, uint16_t *lo, int64_t ldo, int64_t out_pad,
+// Split kernels (np = 2: hi, lo; np = 3: hi, mid, lo). X (rows x cols, ldx)
+// -> np 16-bit planes. Plane rows are written up to `out_pad` >= their
+// length (cols, or rows when transposed), the padding with zeros.
+hipError_t launch_split(int np, int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                        bool transpose, uint16_t *const *planes, int64_t ldo, int64_t out_pad,
                         hipStream_t stream);
 
-// Both operands of the split product in one launch: A (m x k) -> row-major
-// planes (m x kp), B (k x n) -> transposed planes (n x kp); kp a multiple of
-// 8, padding zeroed, plane rows 16-byte aligned.
-hipError_t launch_split_pair(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
-                             const float *B, int64_t ldb, uint16_t *ahi, uint16_t *alo,
-                             uint16_t *bhi, uint16_t *blo, int64_t kp, int64_t ldp,
-                             hipStream_t stream);
+// Both operands of a split product in one launch: A (m x k) -> row-major
+// planes (m x kp), B (k x n) -> transposed planes (n x kp), at row pitch
+// ldp; kp a multiple of 8, padding zeroed, plane rows 16-byte aligned.
+hipError_t launch_split_pair(int np, int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                             const float *B, int64_t ldb, uint16_t *const *ap, uint16_t *const *bp,
+                             int64_t kp, int64_t ldp, hipStream_t stream);
 
 // Grouped: descriptors and tile-queue items live in device memory.
 struct GroupedProblem {          // device-side problem record

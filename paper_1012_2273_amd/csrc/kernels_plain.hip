@@ -62,7 +62,7 @@ template <int P, class S, bool TA, bool TB, bool VEC> static int occupancy_one()
 template <int P, class S, class F> static int by_layout(int layout, bool vec, F &f) {
   if constexpr (!shape_ok<P, S>()) {
     return -1;   // not offered for this precision (the host never picks it)
-  } else if constexpr (P == PREC_SPLIT) {
+  } else if constexpr (P == PREC_SPLIT || P == PREC_SPLIT3) {
     // the split planes are always written K-contiguous and 16-byte aligned
     if (layout != LAYOUT_NT || !vec) return -1;
     return f(KTag<P, S, false, true, true>{});
@@ -102,7 +102,7 @@ template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f)
     case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, f);
     case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, f);
     case CFG_128x256_W8:
-      if constexpr (P == PREC_BF16 || P == PREC_SPLIT)
+      if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3)
         return by_layout<P, S128x256w8>(layout, vec, f);
       else
         return -1;   // 16-bit only (the host never picks it)
@@ -116,6 +116,7 @@ template <class F> static int visit(int prec, int layout, int cfg, bool vec, F &
     case PREC_F32: return by_cfg<PREC_F32>(layout, cfg, vec, f);
     case PREC_BF16: return by_cfg<PREC_BF16>(layout, cfg, vec, f);
     case PREC_SPLIT: return by_cfg<PREC_SPLIT>(layout, cfg, vec, f);
+    case PREC_SPLIT3: return by_cfg<PREC_SPLIT3>(layout, cfg, vec, f);
   }
   return -1;
 }

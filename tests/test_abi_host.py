@@ -85,6 +85,23 @@ def test_split_workspace_size(lib):
     assert lib.gemm_split_workspace_size(2000, 2000, 2000) == 4 * 2000 * 2048 * 2
 
 
+def test_split3_workspace_and_validation(lib):
+    v = ctypes.c_void_p
+    assert lib.gemm_split3_workspace_size(-1, 2, 2) == 0
+    # six planes, rows padded to a 64-element pitch, planes to 256 bytes
+    assert lib.gemm_split3_workspace_size(1, 1, 1) == 6 * 256
+    assert lib.gemm_split3_workspace_size(3, 5, 65) == 3 * 768 + 3 * 1280
+    ws = lib.gemm_split3_workspace_size(8, 8, 8)
+    assert lib.gemm_split3(8, 8, 8, v(16), 8, v(16), 8, v(16), 8, None, ws, None) == _lib.GEMM_EWORKSPACE
+    assert lib.gemm_split3(8, 8, 8, v(16), 8, v(16), 8, v(16), 8, v(256), ws - 1, None) == _lib.GEMM_EWORKSPACE
+    assert lib.gemm_split3(8, 8, 8, v(16), 7, v(16), 8, v(16), 8, v(256), ws, None) == _lib.GEMM_ELD
+    assert lib.gemm_split3(8, 8, -1, v(16), 8, v(16), 8, v(16), 8, v(256), ws, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_split3(8, 8, 8, None, 8, v(16), 8, v(16), 8, v(256), ws, None) == _lib.GEMM_ENULL
+    assert lib.gemm_split3_convert(4, 4, v(16), 4, 2, v(16), v(16), v(16), 4, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_split3_convert(4, 5, v(16), 5, 1, v(16), v(16), v(16), 3, None) == _lib.GEMM_ELD
+    assert lib.gemm_split3_convert(4, 5, v(16), 5, 0, v(16), None, v(16), 5, None) == _lib.GEMM_ENULL
+
+
 def test_split_validation(lib):
     v = ctypes.c_void_p
     ws = lib.gemm_split_workspace_size(8, 8, 8)

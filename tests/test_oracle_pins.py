@@ -302,6 +302,62 @@ def test_split_emulation_rejects_two_term_mistake():
     assert not np.all(np.abs(wrong - C) <= bound)
 
 
+def test_split3_reconstruction_exact():
+    """hi + mid + lo == x exactly for normal binary32 x (24 significand bits
+    in three 8-bit planes), with |x - hi| <= 2^-8 |x| and |x - hi - mid| <=
+    2^-16 |x| (unit roundoff 2^-8 per rounding)."""
+    for x in (inputs.uniform((300, 300), 9, np.float32, 1)[0],
+              inputs.row_scaled(200, 10)[0]):
+        hi, mid, lo = oracle.split3_bf16(x)
+        f = lambda p: oracle.bf16_to_f32(p).astype(np.float64)
+        xd = x.astype(np.float64)
+        assert np.array_equal(hi, oracle.bf16_rne(x))
+        assert np.array_equal(hi, oracle.split_bf16(x)[0])
+        assert np.all(np.abs(xd - f(hi)) <= 2.0 ** -8 * np.abs(xd))
+        assert np.all(np.abs(xd - f(hi) - f(mid)) <= 2.0 ** -16 * np.abs(xd))
+        assert np.array_equal(f(hi) + f(mid) + f(lo), xd)
+
+
+def test_split3_hand_values():
+    """Values whose planes are known: 1 + 2^-10 + 2^-20 splits into 1, 2^-10,
+    2^-20; a bfloat16 value has zero mid and lo; 1 + 2^-9 is a tie that
+    rounds to the even 1, leaving mid = 2^-9."""
+    x = np.array([1 + 2.0 ** -10 + 2.0 ** -20, 3.0, 1 + 2.0 ** -9, -0.5], np.float32)
+    hi, mid, lo = (oracle.bf16_to_f32(p) for p in oracle.split3_bf16(x))
+    assert list(hi) == [1.0, 3.0, 1.0, -0.5]
+    assert list(mid) == [2.0 ** -10, 0.0, 2.0 ** -9, 0.0]
+    assert list(lo) == [2.0 ** -20, 0.0, 0.0, 0.0]
+
+
+def test_split3_emulation_elementwise_bound():
+    """The dropped mid*lo + lo*mid + lo*lo are at most (2 + 3u) u^3 |a||b|
+    (u = 2^-8) and the planes reconstruct A and B exactly, so per entry
+    |C_emul - AB| <= 2.02 * 2^-24 * (|A||B|) (binary64 rounding is far
+    below)."""
+    A, B = inputs.uniform_square(96, 19, dtype=np.float32)
+    Ce = oracle.split3_emul_gemm(A, B)
+    C = oracle.gemm(A, B)
+    absab = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64))
+    assert np.all(np.abs(Ce - C) <= 2.02 * 2.0 ** -24 * absab)
+    assert oracle.relerr_fro(Ce, C) < 2e-8
+    # an order of magnitude beyond the two-term split on the same inputs
+    assert oracle.relerr_fro(Ce, C) < 0.05 * oracle.relerr_fro(oracle.split_emul_gemm(A, B), C)
+
+
+def test_split3_emulation_rejects_dropped_term():
+    """Leaving out mid*mid (or using the two-term planes) breaks the bound."""
+    A, B = inputs.uniform_square(96, 19, dtype=np.float32)
+    f = oracle.bf16_to_f32
+    ah, am, al = (f(p) for p in oracle.split3_bf16(A))
+    bh, bm, bl = (f(p) for p in oracle.split3_bf16(B))
+    C = oracle.gemm(A, B)
+    bound = 2.02 * 2.0 ** -24 * (np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)))
+    wrong = (oracle.gemm(al, bh) + oracle.gemm(ah, bl) + oracle.gemm(am, bh)
+             + oracle.gemm(ah, bm) + oracle.gemm(ah, bh))
+    assert not np.all(np.abs(wrong - C) <= bound)
+    assert not np.all(np.abs(oracle.split_emul_gemm(A, B) - C) <= bound)
+
+
 # ------------------------------------------------------------------ backward
 
 def test_backward_central_difference_fp64_n16():
