@@ -14,6 +14,7 @@ seeded synthetic inputs:
            of the captured persistent launch (tuned policy); the same 512
            products as 512 single launches are timed after the step loop
            and reported beside it (loop_ms, speedup_vs_loop)
+  grouped_fp32  the same batch in binary32
 Each path is bracketed by HIP events on torch's current stream (the stream
 the kernels run on); the step loop is bracketed by device synchronisation.
 ``value`` is the binary64 rate 2N^3/t at N = 2000; the split rate and every
@@ -51,7 +52,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # TFLOP/s, dense MFMA
 HBM_PEAK = 8000.0                                    # GB/s
 METRIC = "GFLOP/s (2N^3/t) at N=2000 FP64 vs split-BF16, at stated rel. error"
-ALL_PATHS = ["fp64", "split", "split3", "fp32", "bf16", "backward", "grouped"]
+ALL_PATHS = ["fp64", "split", "split3", "fp32", "bf16", "backward", "grouped", "grouped_fp32"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fp64_n2000.json")
 # the binary64 kernel's code and the host choice of its tile shape
 KERNEL_SOURCES = ["paper_1012_2273_amd/csrc/gemm_tile.hpp",
@@ -341,23 +342,25 @@ def main():
             bw_out["d"] = G.gemm_backward(Abd, Bbd, Wbd)
         work["backward"] = (run_bw, 2 * 2.0 * NB ** 3)
 
-    plan = None
-    if "grouped" in paths:
-        log("generating 512-problem batch")
+    gp = {}   # grouped path -> its plan, device operands and host problems
+    for gpath, gdt in (("grouped", np.float64), ("grouped_fp32", np.float32)):
+        if gpath not in paths:
+            continue
+        log(f"generating 512-problem batch ({gpath})")
         sizes = inputs.batch_sizes(512, 3_000_000)
         gA, gB, gprobs = [], [], []
         for i, n in enumerate(sizes):
-            A, B = inputs.batch_problem(i, int(n), 3_000_000, np.float64)
+            A, B = inputs.batch_problem(i, int(n), 3_000_000, gdt)
             gprobs.append((A, B))
             gA.append(torch.from_numpy(A).to(dev))
             gB.append(torch.from_numpy(B).to(dev))
-        host["grouped"] = (sizes, gprobs)
         import tempfile
         cache = os.path.join(tempfile.mkdtemp(prefix="gemm_tune_"), "tune_cache.json")
         t0 = time.time()
         plan = G.GroupedPlan(gA, gB, autotune=True, tune_cache=cache)
-        log(f"grouped plan (autotune) {time.time() - t0:.2f}s; tiles/policy {plan.info()}")
-        work["grouped"] = (plan.run, float(sum(2 * int(n) ** 3 for n in sizes)))
+        log(f"{gpath} plan (autotune) {time.time() - t0:.2f}s; tiles/policy {plan.info()}")
+        gp[gpath] = {"plan": plan, "A": gA, "B": gB, "sizes": sizes, "probs": gprobs}
+        work[gpath] = (plan.run, float(sum(2 * int(n) ** 3 for n in sizes)))
 
     order = [p for p in ALL_PATHS if p in paths]
 
@@ -393,12 +396,12 @@ def main():
     ms_min = {p: float(np.min([a.elapsed_time(b) for a, b in evs[p]])) for p in order}
 
     # ------------------------------------- grouped versus one launch per product
-    loop = None
-    if "grouped" in order:
-        gC = [torch.empty_like(a) for a in gA]
+    loop = {}
+    for gpath, g in gp.items():
+        gC = [torch.empty_like(a) for a in g["A"]]
 
         def run_loop():
-            for a, b, c in zip(gA, gB, gC):
+            for a, b, c in zip(g["A"], g["B"], gC):
                 G.gemm_plain(a, b, c)
         run_loop()
         torch.cuda.synchronize()
@@ -411,7 +414,7 @@ def main():
             e1.record(stream)
             le.append((e0, e1))
         torch.cuda.synchronize()
-        loop = float(np.mean([a.elapsed_time(b) for a, b in le]))
+        loop[gpath] = float(np.mean([a.elapsed_time(b) for a, b in le]))
         del gC
 
     # ---------------------------------------------------------- error check
@@ -440,18 +443,17 @@ def main():
             eA = _relerr(dA[r, c], _entries(Wb, Bb.T, r, c))
             eB = _relerr(dB[r, c], _entries(Ab.T, Wb, r, c))
             errs["backward"] = max(eA, eB)
-        if "grouped" in order:
-            sizes, gprobs = host["grouped"]
+        for gpath, gd in gp.items():
             worst = 0.0
             g = np.random.Generator(np.random.PCG64(2))
-            for i in range(0, len(sizes), 4):
-                A, B = gprobs[i]
-                n = int(sizes[i])
+            for i in range(0, len(gd["sizes"]), 4):
+                A, B = gd["probs"][i]
+                n = int(gd["sizes"][i])
                 r = g.integers(0, n, 40)
                 c = g.integers(0, n, 40)
-                got = plan.Cs[i].cpu().numpy()[r, c]
+                got = gd["plan"].Cs[i].cpu().double().numpy()[r, c]
                 worst = max(worst, _relerr(got, _entries(A, B, r, c)))
-            errs["grouped"] = worst
+            errs[gpath] = worst
 
     # ---------------------------------------------------------- cpu baseline
     cpu = None
@@ -494,10 +496,10 @@ def main():
         if p in errs:
             d["rel_err"] = float(f"{errs[p]:.3e}")
         paths_out[p] = d
-    if loop is not None:
-        paths_out["grouped"]["loop_ms"] = round(loop, 4)
-        paths_out["grouped"]["loop_gflops"] = round(work["grouped"][1] / (loop * 1e-3) / 1e9, 2)
-        paths_out["grouped"]["speedup_vs_loop"] = round(loop / ms["grouped"], 3)
+    for gpath, lm in loop.items():
+        paths_out[gpath]["loop_ms"] = round(lm, 4)
+        paths_out[gpath]["loop_gflops"] = round(work[gpath][1] / (lm * 1e-3) / 1e9, 2)
+        paths_out[gpath]["speedup_vs_loop"] = round(lm / ms[gpath], 3)
     if "split" in paths_out:
         paths_out["split"]["mfma_util_bf16"] = round(
             6.0 * N ** 3 / (ms["split"] * 1e-3) / 1e12 / PEAK["bf16"], 4)
@@ -538,8 +540,8 @@ def main():
         "host": hinfo,
     }
     print(json.dumps(line), flush=True)
-    if plan is not None:
-        plan.close()
+    for g in gp.values():
+        g["plan"].close()
 
 
 if __name__ == "__main__":
