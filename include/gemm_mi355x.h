@@ -66,7 +66,9 @@ enum {
  *   A, lda  device, m rows of k elements, lda >= k.
  *   B, ldb  device, k rows of n elements, ldb >= n.
  *   C, ldc  device, m rows of n elements, ldc >= n; overwritten.
- * Errors: EINVAL (m, n or k < 0), ENULL, ELD, EUNSUPPORTED (dtype), EHIP.
+ * Row pitches of A and B (ld times the element size) must be below 8 MiB.
+ * Errors: EINVAL (m, n or k < 0, or a row pitch of 8 MiB or more), ENULL,
+ * ELD, EUNSUPPORTED (dtype), EHIP.
  */
 int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k,
                const void *A, int64_t lda, const void *B, int64_t ldb,

@@ -183,12 +183,14 @@ static bool vec_ok(const void *p, int64_t ld, size_t es, int64_t contiguous_exte
          (contiguous_extent % v == 0);
 }
 
-// Operand offsets inside a tile are 32-bit: 128 rows of ld elements must
-// span less than 2^31 bytes.
+// Operand offsets inside a tile are 32-bit and offsets from 2^31 on read as
+// zeros: the largest tile (256 rows of the 128 x 256 shape) must span less
+// than 2^31 bytes, so row pitches stay below 8 MiB.
+constexpr uint64_t kMaxPitch = 1ull << 23;
 static int check_ld_range(const char *name, int64_t ld, size_t es) {
-  if ((uint64_t)ld * es >= (1ull << 24))
+  if ((uint64_t)ld * es >= kMaxPitch)
     return set_error(GEMM_EINVAL, std::string("leading dimension of ") + name +
-                                      " too large (row pitch must be below 16 MiB)");
+                                      " too large (row pitch must be below 8 MiB)");
   return GEMM_OK;
 }
 
@@ -359,6 +361,8 @@ static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A
   int64_t kp, ldp;
   size_t off[6], total;
   split_layout(np, m, n, k, kp, ldp, off, total);
+  if ((uint64_t)ldp * 2 >= kMaxPitch)
+    return set_error(GEMM_EINVAL, "k too large (plane row pitch must be below 8 MiB)");
   if (workspace == nullptr || workspace_bytes < total)
     return set_error(GEMM_EWORKSPACE, "need " + std::to_string(total) + " bytes, got " +
                                           std::to_string(workspace_bytes));

@@ -292,6 +292,8 @@ static int validate_problems(int dtype, const gemm_problem *probs, int32_t count
     }
     if (q.lda < q.k || q.ldb < q.n || q.ldc < q.n)
       return set_error(GEMM_ELD, "leading dimension too small" + at);
+    // the grouped shapes have at most 128 rows per operand tile: 32-bit tile
+    // offsets stay below 2^31 for row pitches below 16 MiB
     const uint64_t es = dtype == GEMM_F64 ? 8 : 4;
     if ((uint64_t)q.lda * es >= (1ull << 24) || (uint64_t)q.ldb * es >= (1ull << 24))
       return set_error(GEMM_EINVAL, "leading dimension too large (row pitch must be below 16 MiB)" + at);

@@ -85,6 +85,17 @@ def test_split_workspace_size(lib):
     assert lib.gemm_split_workspace_size(2000, 2000, 2000) == 4 * 2000 * 2048 * 2
 
 
+def test_row_pitch_limit(lib):
+    """Tile offsets are 32-bit: row pitches of 8 MiB or more are rejected
+    before any launch (a 256-row tile must span less than 2^31 bytes)."""
+    v = ctypes.c_void_p
+    assert _plain(lib, 0, 4, 4, 4, lda=1 << 20) == _lib.GEMM_EINVAL          # 8 MiB binary64 rows
+    assert _plain(lib, 1, 4, 4, 4, ldb=1 << 21) == _lib.GEMM_EINVAL          # 8 MiB binary32 rows
+    k = 1 << 22                                                              # split planes: 8 MiB rows
+    assert lib.gemm_split(4, 4, k, v(16), k, v(16), 4, v(16), 4, v(256), 1 << 40, None) == _lib.GEMM_EINVAL
+    assert lib.gemm_split3(4, 4, k, v(16), k, v(16), 4, v(16), 4, v(256), 1 << 40, None) == _lib.GEMM_EINVAL
+
+
 def test_split3_workspace_and_validation(lib):
     v = ctypes.c_void_p
     assert lib.gemm_split3_workspace_size(-1, 2, 2) == 0
