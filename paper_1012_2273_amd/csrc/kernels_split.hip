@@ -131,7 +131,11 @@ __device__ __forceinline__ void load4(const float *X, int64_t ldx, int64_t rows,
 template <bool VEC, int NP>
 __global__ void __launch_bounds__(256)
 split_pair_kernel(SplitJob<NP> a, SplitJob<NP> b, int64_t na) {
-  constexpr int T = 64, PITCH = T + 8;
+  // 132-byte rows: the transposed reads below take one column of rows
+  // rv, rv + 8, ..., rv + 56 in 8 neighbouring lanes, which a 132-byte pitch
+  // spreads over 8 different 32-byte bank windows (a 144-byte pitch put them
+  // in two: 82% of the LDS cycles were bank conflicts)
+  constexpr int T = 64, PITCH = T + 2;
   __shared__ __attribute__((aligned(16))) uint16_t sh[NP][T][PITCH];
   const int tid = threadIdx.x;
   if ((int64_t)blockIdx.x < na) {
