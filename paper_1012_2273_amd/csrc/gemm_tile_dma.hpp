@@ -98,6 +98,7 @@ struct DmaOp {
                              (!KC || RB <= 256) && (KC || (CPR & (CPR - 1)) == 0) && LG >= 1;
 
   uint32_t off[PERW > 0 ? PERW : 1];
+  uint32_t offr[PERW > 0 ? PERW : 1];  // off, or kOob outside the matrix's M/N extent
   int32_t kk[PERW > 0 ? PERW : 1];   // K index of the chunk (first element)
   bool rok[PERW > 0 ? PERW : 1];     // M/N index inside the matrix
 
@@ -134,6 +135,7 @@ struct DmaOp {
         kk[j] = r;
         rok[j] = r0 + m < rtot;
       }
+      offr[j] = rok[j] ? off[j] : kOob;
     }
   }
 
@@ -151,12 +153,15 @@ struct DmaOp {
   }
 
   // Transfer j of this wave for the K-tile at tile_base (see issue()).
-  __device__ __forceinline__ void issue_one(int j, const srd_t &srd, int64_t k0, int64_t K,
-                                            uint32_t base, int wave) const {
-    const bool ok = rok[j] && (k0 + kk[j] < K);
-    const uint32_t dst = __builtin_amdgcn_readfirstlane(base + (uint32_t)(wave + j * NW) * 1024u);
+  // krem = K - k0 clamped to int32 (the same on every lane); wave must be
+  // wave-uniform (an SGPR value), which keeps the LDS destination scalar
+  // arithmetic. offr holds the offset with the M/N edge already applied.
+  __device__ __forceinline__ void issue_one(int j, const srd_t &srd, int32_t krem, uint32_t base,
+                                            int wave) const {
+    const uint32_t dst = base + (uint32_t)(wave + j * NW) * 1024u;
+    const uint32_t voff = kk[j] < krem ? offr[j] : kOob;
     __builtin_amdgcn_sched_barrier(0);
-    lds_dma16(srd, ok ? off[j] : kOob, dst);
+    lds_dma16(srd, voff, dst);
     __builtin_amdgcn_sched_barrier(0);
   }
 
@@ -290,7 +295,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   constexpr int NS = Plan::NS, D = NS - 1;     // ring stages, transfer distance in tiles
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform, in an SGPR
   const int wpos = wave % (S::WM * S::WN), kh = wave / (S::WM * S::WN);
   const int wm = wpos % S::WM, wn = wpos / S::WM;
   const int lr = lane % MB, lgp = lane / MB;
@@ -358,11 +364,15 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   using TM = Terms<PL>;
   constexpr int MPB = SPU * TM::N;                      // MFMAs per block per unit
   constexpr int NPRE = MPB * ((U - 1) * NB + NB1);       // pre-barrier MFMAs per tile
-  struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; bool on; };
+  struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; int32_t krem; bool on; };
   Pending pend;
   auto prep_tile = [&](int64_t kt, int st) {
     pend.on = kt < KT;
     if (!pend.on) return;
+    {
+      const int64_t rem = g.K - kt * BK;
+      pend.krem = rem > 0x7fffffff ? 0x7fffffff : (int32_t)rem;
+    }
     pend.k0 = kt * BK;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
@@ -380,9 +390,9 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     constexpr int pl = k / per_plane, r = k % per_plane;
     if (pend.on) {
       if constexpr (r < OA::PERW)
-        oa.issue_one(r, pend.sa[pl], pend.k0, g.K, pend.la[pl], wave);
+        oa.issue_one(r, pend.sa[pl], pend.krem, pend.la[pl], wave);
       else
-        ob.issue_one(r - OA::PERW, pend.sb[pl], pend.k0, g.K, pend.lb[pl], wave);
+        ob.issue_one(r - OA::PERW, pend.sb[pl], pend.krem, pend.lb[pl], wave);
     }
   };
   // pre-barrier MFMA number n: issue every transfer k with k * NPRE / (2 DPW) == n
