@@ -108,12 +108,30 @@ int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
  *              bytes, owned by the caller, 16-byte aligned; it holds the
  *              planes between the split launch and the product launch, so it
  *              must not be shared by overlapping calls.
+ * Small products (see gemm_split_one_launch) run as one launch that splits
+ * each operand fragment in registers instead; the result is the same bit
+ * for bit and the workspace is then left untouched (it is still required).
  * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
  */
 int gemm_split(int64_t m, int64_t n, int64_t k,
                const float *A, int64_t lda, const float *B, int64_t ldb,
                float *C, int64_t ldc, void *workspace, size_t workspace_bytes,
                void *stream);
+
+/*
+ * gemm_split_one_launch -- 1 if gemm_split and gemm_split3 with these
+ * arguments run as one launch that splits each fragment in registers, 0 if
+ * they run the split step and then the plane product (or if the arguments
+ * are empty or null; nothing is validated or launched). The one-launch form
+ * needs A and B 16-byte aligned with row pitches of a multiple of 16 bytes,
+ * k and n multiples of 4, k <= 1024 and at most one 128 x 128 output tile
+ * per two CUs of the current device: there the separate split step costs
+ * more than repeating the conversion in every wave that reads a fragment.
+ * Both forms give the same result bit for bit (Section 3.1, Algorithm 1 with
+ * the split operands of gemm_split / gemm_split3).
+ */
+int gemm_split_one_launch(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                          const float *B, int64_t ldb);
 
 /*
  * gemm_split3_workspace_size -- bytes of device workspace gemm_split3 needs
@@ -145,7 +163,8 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
  * bfloat16 matrix cores; the higher-accuracy variant of gemm_split.
  *   workspace  device memory of at least gemm_split3_workspace_size(m, n, k)
  *              bytes, owned by the caller, 16-byte aligned, not shared by
- *              overlapping calls.
+ *              overlapping calls. Small products run as one launch, as for
+ *              gemm_split.
  * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
  */
 int gemm_split3(int64_t m, int64_t n, int64_t k,

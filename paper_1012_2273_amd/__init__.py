@@ -20,6 +20,7 @@ from ._lib import (GEMM_BF16, GEMM_F32, GEMM_F64, GEMM_PLAN_AUTOTUNE, GEMM_PLAN_
 
 __all__ = [
     "gemm_plain", "gemm_split", "gemm_split_convert", "gemm_split_workspace_size",
+    "gemm_split3", "gemm_split3_convert", "gemm_split3_workspace_size", "split_one_launch",
     "gemm_backward", "gemm_grouped", "GroupedPlan", "GemmFn", "matmul", "load",
     "GemmError", "GemmArgError", "GEMM_F64", "GEMM_F32", "GEMM_BF16",
     "tile_configs", "force_tile_config",
@@ -121,6 +122,19 @@ def _split_product(name, size_fn, A, B, C, workspace):
                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                   _stream(A)), name)
     return C
+
+
+def split_one_launch(A, B):
+    """True if gemm_split / gemm_split3 on these operands run as one launch
+    that splits each fragment in registers (small products), False if they
+    run the split step and then the plane product."""
+    m, k = A.shape
+    n = B.shape[1]
+    if m == 0 or n == 0:
+        return False
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    return bool(_lib.load().gemm_split_one_launch(m, n, k, pa, lda, pb, ldb))
 
 
 def gemm_split(A, B, C=None, workspace=None):

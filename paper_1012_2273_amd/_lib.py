@@ -20,7 +20,7 @@ GEMM_PLAN_AUTOTUNE, GEMM_PLAN_NO_GRAPH = 1, 2
 # every symbol the header declares; the CPU tests check they are exported
 EXPORTS = (
     "gemm_plain", "gemm_split_workspace_size", "gemm_split_convert", "gemm_split",
-    "gemm_split3_workspace_size", "gemm_split3_convert", "gemm_split3",
+    "gemm_split3_workspace_size", "gemm_split3_convert", "gemm_split3", "gemm_split_one_launch",
     "gemm_backward", "gemm_grouped_plan_create", "gemm_grouped_run",
     "gemm_grouped_plan_update", "gemm_grouped_plan_destroy", "gemm_grouped_plan_info",
     "gemm_grouped", "gemm_strerror", "gemm_last_error", "gemm_tile_config_count",
@@ -60,6 +60,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
             "gemm_split3_workspace_size": (sz, [i64, i64, i64]),
             "gemm_split3_convert": (ci, [i64, i64, vp, i64, ci, vp, vp, vp, i64, vp]),
             "gemm_split3": (ci, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
+            "gemm_split_one_launch": (ci, [i64, i64, i64, vp, i64, vp, i64]),
             "gemm_backward": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64,
                                    vp, i64, vp]),
             "gemm_grouped_plan_create": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(GemmProblem),

@@ -40,11 +40,11 @@ static std::atomic<int> g_force_cfg{-1};
 
 // The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
-// The 128x256w8 shape is 16-bit only.
+// The 128x256w8 shape is offered to the bfloat16-MFMA products only.
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
-  if (cfg == CFG_128x256_W8) return prec == PREC_BF16 || prec == PREC_SPLIT || prec == PREC_SPLIT3;
+  if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
   return true;
 }
 bool cfg_grouped(int cfg) {
@@ -155,7 +155,9 @@ static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int
 // says it is at least 15% faster.
 static int choose_cfg(int prec, int layout, bool vec, int64_t m, int64_t n) {
   const int forced = g_force_cfg.load();
-  if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced)) return forced;
+  if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced) &&
+      plain_offered(prec, layout, forced, vec))
+    return forced;
   const int pick = choose_rule(prec, m, n);
   if (prec != PREC_F64 && prec != PREC_F32) return pick;
   const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
@@ -348,6 +350,20 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 
 // The split product with np planes per operand: one split launch for both
 // operands into the caller's workspace, then the product of the planes.
+// The one-launch form of the split products (each fragment split in
+// registers between the LDS read and the MFMAs) repeats the conversion in
+// every wave that reads a fragment: it wins while the separate split step's
+// launch and pass over A and B cost more than that, i.e. for products that
+// leave most CUs idle and have a short K loop (N <= 1000: 1.2-1.6x faster;
+// N = 1500: 7% slower, N = 2000: 18% slower, both precisions). It needs
+// operands fit for 16-byte direct-to-LDS transfers.
+static bool split_one_launch(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                             const void *B, int64_t ldb) {
+  if (!vec_ok(A, lda, 4, k) || !vec_ok(B, ldb, 4, n) || k > 1024) return false;
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  return 2 * t128 <= (int64_t)device_cus();
+}
+
 static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                          const float *B, int64_t ldb, float *C, int64_t ldc, void *workspace,
                          size_t workspace_bytes, void *stream) {
@@ -369,6 +385,12 @@ static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A
   if ((uintptr_t)workspace % 16 != 0)
     return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
+  // Small products: one launch that splits each fragment in registers
+  // (the same result bit for bit, no planes).
+  if (split_one_launch(m, n, k, A, lda, B, ldb)) {
+    GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
+    return run_product(np == 2 ? PREC_FSPLIT : PREC_FSPLIT3, LAYOUT_NN, a, 4, s);
+  }
   char *ws = (char *)workspace;
   uint16_t *ap[3] = {nullptr, nullptr, nullptr}, *bp[3] = {nullptr, nullptr, nullptr};
   for (int p = 0; p < np; ++p) {
@@ -384,6 +406,13 @@ static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A
   }
   GemmArgs a{m, n, k > 0 ? kp : 0, ap[0], ldp, bp[0], ldp, ap[1], bp[1], C, ldc, ap[2], bp[2]};
   return run_product(np == 2 ? PREC_SPLIT : PREC_SPLIT3, LAYOUT_NT, a, 2, s);
+}
+
+int gemm_split_one_launch(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                          const float *B, int64_t ldb) {
+  clear_error();
+  if (m <= 0 || n <= 0 || k < 0 || A == nullptr || B == nullptr) return 0;
+  return split_one_launch(m, n, k, A, lda, B, ldb) ? 1 : 0;
 }
 
 int gemm_split(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,

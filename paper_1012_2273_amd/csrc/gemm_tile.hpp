@@ -40,7 +40,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3, PREC_SPLIT3 = 4 };
+enum Prec : int {
+  PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3, PREC_SPLIT3 = 4,
+  PREC_FSPLIT = 5, PREC_FSPLIT3 = 6   // split in registers from binary32 tiles
+};
 
 // Per-precision description of the MFMA used and the element types.
 //   E    element type in global memory and LDS (bf16 kept as 16-bit pattern)
@@ -51,27 +54,56 @@ enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3, PRE
 //   GRP  rows per lane group in the 16x16 output block: lane l holds column
 //        l%16 and rows (q/GRP)*4*GRP + (l/16)*GRP + q%GRP, q = 0..3
 //        (binary64: rows 4q + l/16; binary32 accumulators: rows 4(l/16) + q)
+//   CVT  bfloat16 terms each binary32 element is split into in registers
+//        between the LDS read and the MFMA (0: operands used as loaded)
 template <int P> struct Traits;
 template <> struct Traits<PREC_F64> {
   using E = double; using Op = double; using Acc = f64x4; using Out = double;
-  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 1;
+  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 1, CVT = 0;
 };
 template <> struct Traits<PREC_F32> {
   using E = float; using Op = float; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 4;
+  static constexpr int KPL = 1, BK = 16, PLANES = 1, GRP = 4, CVT = 0;
 };
 template <> struct Traits<PREC_BF16> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4;
+  static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4, CVT = 0;
 };
 template <> struct Traits<PREC_SPLIT> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 64, PLANES = 2, GRP = 4;   // hi and lo planes
+  static constexpr int KPL = 8, BK = 64, PLANES = 2, GRP = 4, CVT = 0;   // hi and lo planes
 };
 template <> struct Traits<PREC_SPLIT3> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 32, PLANES = 3, GRP = 4;   // hi, mid and lo planes
+  static constexpr int KPL = 8, BK = 32, PLANES = 3, GRP = 4, CVT = 0;   // hi, mid and lo planes
 };
+// The same two products with the split done per fragment in registers: the
+// operands are the binary32 matrices themselves, the K-tile depths and the
+// MFMA order are those of the plane products, so the results are the same
+// bit for bit.
+template <> struct Traits<PREC_FSPLIT> {
+  using E = float; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 64, PLANES = 1, GRP = 4, CVT = 2;
+};
+template <> struct Traits<PREC_FSPLIT3> {
+  using E = float; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4, CVT = 3;
+};
+
+// x split into NP bfloat16 terms, each rounded to nearest even from what the
+// earlier terms leave (Dekker-style splitting): t0 = bf16(x), t1 = bf16(x -
+// t0), t2 = bf16(x - t0 - t1). Every subtraction is exact in binary32 (the
+// remainder fits in 24 bits), so the terms are unique. Used by the split
+// step and by the in-register split of the fused products alike.
+template <int NP> __device__ __forceinline__ void split_x(float x, uint16_t (&o)[NP]) {
+  float r = x;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const __bf16 b = (__bf16)r;
+    o[p] = __builtin_bit_cast(uint16_t, b);
+    if (p + 1 < NP) r = r - (float)b;
+  }
+}
 
 // The products of a split precision, as (A plane, B plane) pairs in the
 // order they are accumulated: smallest terms first, so that the large ones

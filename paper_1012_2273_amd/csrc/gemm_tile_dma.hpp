@@ -79,8 +79,9 @@ __device__ __forceinline__ void raw_barrier() {
 }
 
 // One operand plane of one K-tile: R rows (M or N) x BK. LG: K rows
-// between the lane groups of one LDS read (MN layout swizzle).
-template <typename E, int R, int BK, int NT, bool KC, int LG>
+// between the lane groups of one LDS read, MBW: lanes per lane group (the
+// MFMA block width; both set the MN layout swizzle).
+template <typename E, int R, int BK, int NT, bool KC, int LG, int MBW = 16>
 struct DmaOp {
   static constexpr int ES = (int)sizeof(E);
   static constexpr int V = 16 / ES;                  // elements per chunk
@@ -105,9 +106,9 @@ struct DmaOp {
   __device__ __forceinline__ static int swz(int r) { return ((r * RB) >> 8) % CPR; }
   // MN rows. 16-bit elements: rows k .. k+3 of one transposing read put
   // their 32-byte column blocks in four different 32-byte bank groups.
-  // 4- and 8-byte elements: the four lane groups of a read take rows LG
-  // apart, 16 consecutive elements each; shifting row k's chunks by
-  // (k / LG) % 4 such spans puts the four groups on different banks.
+  // 4- and 8-byte elements: the 64 / MBW lane groups of a read take rows LG
+  // apart, MBW consecutive elements each; moving row k's chunks by
+  // (k / LG) % (64 / MBW) such spans puts the groups on different banks.
   __device__ __forceinline__ static int swzm(int r) {
     if constexpr (KC) return 0;
     else if constexpr (TR) {
@@ -115,7 +116,8 @@ struct DmaOp {
       else if constexpr (CPR >= 4) return 2 * (r % 2);
       else return 0;
     } else {
-      return (((r / LG) & 3) * ES) & (CPR - 1);
+      constexpr int NGR = 64 / MBW, SPAN = MBW * ES / 16;
+      return (((r / LG) & (NGR - 1)) * SPAN) & (CPR - 1);
     }
   }
 
@@ -168,11 +170,22 @@ struct DmaOp {
   // RU consecutive K elements (K offset koff, a multiple of RU) of LDS row
   // `row` (KC) or column `row` (MN). For TR the 16 lanes of a group must
   // ask for 16 consecutive columns starting at a multiple of 16, lane i for
-  // column start + i, all at the same koff.
+  // column start + i, all at the same koff. KC reads of more than one
+  // chunk read each chunk at its own swizzled place.
   template <int RU>
   __device__ __forceinline__ static VecT<E, RU> read(const char *region, int row, int koff) {
     VecT<E, RU> v;
-    if constexpr (KC) {
+    if constexpr (KC && RU > V) {
+      static_assert(RU % V == 0, "whole chunks");
+      using Chunk = VecT<E, V>;
+#pragma unroll
+      for (int h = 0; h < RU / V; ++h) {
+        const Chunk c = *reinterpret_cast<const Chunk *>(
+            region + row * RB + (((koff / V + h) ^ swz(row)) * 16));
+#pragma unroll
+        for (int e = 0; e < V; ++e) v.e[h * V + e] = c.e[e];
+      }
+    } else if constexpr (KC) {
       const int c = koff / V, e0 = koff % V;
       v = *reinterpret_cast<const VecT<E, RU> *>(region + row * RB + ((c ^ swz(row)) * 16) + e0 * ES);
     } else if constexpr (TR) {
@@ -237,8 +250,8 @@ template <int DPW, int MAXT> __device__ __forceinline__ void wait_tiles(int n) {
 template <int P, class S, bool TA, bool TB> struct DmaPlan {
   using T = Traits<P>;
   using E = typename T::E;
-  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA, Geom<P, S>::KG>;
-  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB, Geom<P, S>::KG>;
+  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA, Geom<P, S>::KG, Geom<P, S>::MB>;
+  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB, Geom<P, S>::KG, Geom<P, S>::MB>;
   static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
   // Ring depth: transfers run NS - 1 K-tiles ahead of the MFMAs. binary64
@@ -269,6 +282,28 @@ template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr int ld
   return stages > red ? stages : red;
 }
 
+// split_x for two elements at once: each term is one packed round-to-
+// nearest-even conversion of the pair (v_cvt_pk_bf16_f32, the instruction
+// the scalar conversion uses too), widened back to binary32 by a shift or a
+// mask and subtracted exactly. o[p] holds term p of x0 in its low and of x1
+// in its high 16 bits.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <int NP>
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t (&o)[NP]) {
+  float r0 = x0, r1 = x1;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const f32x2 r = {r0, r1};
+    const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+    o[p] = w;
+    if (p + 1 < NP) {
+      r0 = r0 - __builtin_bit_cast(float, w << 16);
+      r1 = r1 - __builtin_bit_cast(float, w & 0xffff0000u);
+    }
+  }
+}
+
 // Compute one BM x BN tile of C at (m0, n0) with direct-to-LDS operands.
 // Same contract as gemm_tile with VEC = true.
 template <int P, class S, bool TA, bool TB>
@@ -288,8 +323,10 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   constexpr int MB = GM::MB, FM = GM::FM, FN = GM::FN, NR = GM::NR;
   constexpr int KG = GM::KG, KW = KG / KS;
   constexpr int VE = 16 / (int)sizeof(E);
-  constexpr int RU = VE < KW ? VE : KW;
+  constexpr int RU0 = VE < KW ? VE : KW;
+  constexpr int RU = RU0 < KPL ? KPL : RU0;     // at least one MFMA operand
   constexpr int U = KW / RU, SPU = RU / KPL;
+  constexpr int CV = T::CVT;
   constexpr int NB = FM * FN, NB1 = NB / 2;
   constexpr int STAGE = Plan::STAGE, DPW = Plan::PER_WAVE;
   constexpr int NS = Plan::NS, D = NS - 1;     // ring stages, transfer distance in tiles
@@ -347,8 +384,39 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
         fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * MB + lr, koff);
     }
   };
-  auto op_of = [](const Unit &u, int step) {
+  auto op_of = [](const auto &u, int step) {
     return *reinterpret_cast<const Op *>(&u.e[step * KPL]);
+  };
+  // In-register split (CV > 0): the bfloat16 terms of the current unit's
+  // binary32 fragments, made right before the unit's MFMAs, two elements at
+  // a time (bfloat16 pairs packed in 32 bits).
+  using Half = VecT<uint32_t, (RU / 2 > 0 ? RU / 2 : 1)>;
+  Half ca[CV > 0 ? CV : 1][FM], cb[CV > 0 ? CV : 1][FN];
+  auto op_h = [](const Half &u, int step) {
+    return *reinterpret_cast<const Op *>(&u.e[step * KPL / 2]);
+  };
+  auto convert = [&](auto buf_tag) {
+    constexpr int b = decltype(buf_tag)::value;
+    if constexpr (CV > 0) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int q = 0; q < RU / 2; ++q) {
+          uint32_t t[CV];
+          split_pair<CV>((float)fa[b][0][i].e[2 * q], (float)fa[b][0][i].e[2 * q + 1], t);
+#pragma unroll
+          for (int p = 0; p < CV; ++p) ca[p][i].e[q] = t[p];
+        }
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int q = 0; q < RU / 2; ++q) {
+          uint32_t t[CV];
+          split_pair<CV>((float)fb[b][0][j].e[2 * q], (float)fb[b][0][j].e[2 * q + 1], t);
+#pragma unroll
+          for (int p = 0; p < CV; ++p) cb[p][j].e[q] = t[p];
+        }
+    }
   };
 
   // Issue of the transfers of the K-tile D ahead. binary64/binary32: spread
@@ -361,7 +429,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   // MFMAs take about as long as the transfers themselves at the L2 -> CU
   // rate (measured 8-10% faster than spreading).
   constexpr bool BURST = KPL == 8;
-  using TM = Terms<PL>;
+  using TM = Terms<(CV > 0 ? CV : PL)>;
   constexpr int MPB = SPU * TM::N;                      // MFMAs per block per unit
   constexpr int NPRE = MPB * ((U - 1) * NB + NB1);       // pre-barrier MFMAs per tile
   struct Pending { srd_t sa[PL], sb[PL]; uint32_t la[PL], lb[PL]; int64_t k0; int32_t krem; bool on; };
@@ -410,14 +478,19 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     constexpr int lo = decltype(lo_tag)::value, hi = decltype(hi_tag)::value;
     constexpr int SLOT = decltype(slot_tag)::value;
     constexpr int NX = hi - lo;
+    if constexpr (CV > 0 && lo == 0) convert(buf_tag);
     [&]<int... m>(std::integer_sequence<int, m...>) {
       (([&] {
          constexpr int st = m / (TM::N * NX);
-         constexpr int term = (m / NX) % TM::N;   // Terms<PL> order, smallest first
+         constexpr int term = (m / NX) % TM::N;   // Terms order, smallest first
          constexpr int x = lo + m % NX;
          if constexpr (SLOT >= 0) maybe_issue(std::integral_constant<int, SLOT + m>{});
-         mfma(acc[x / FN][x % FN], op_of(fa[b][TM::a[term]][x / FN], st),
-              op_of(fb[b][TM::b[term]][x % FN], st));
+         if constexpr (CV > 0)
+           mfma(acc[x / FN][x % FN], op_h(ca[TM::a[term]][x / FN], st),
+                op_h(cb[TM::b[term]][x % FN], st));
+         else
+           mfma(acc[x / FN][x % FN], op_of(fa[b][TM::a[term]][x / FN], st),
+                op_of(fb[b][TM::b[term]][x % FN], st));
        }()), ...);
     }(std::make_integer_sequence<int, SPU * TM::N * NX>{});
   };

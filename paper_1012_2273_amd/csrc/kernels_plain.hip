@@ -66,6 +66,15 @@ template <int P, class S, class F> static int by_layout(int layout, bool vec, F 
     // the split planes are always written K-contiguous and 16-byte aligned
     if (layout != LAYOUT_NT || !vec) return -1;
     return f(KTag<P, S, false, true, true>{});
+  } else if constexpr (P == PREC_FSPLIT || P == PREC_FSPLIT3) {
+    // binary32 operands as given, direct-to-LDS only (the caller falls back
+    // to the split step and the plane product otherwise)
+    if constexpr (!dma_ok<P, S, false, false>()) {
+      return -1;
+    } else {
+      if (layout != LAYOUT_NN || !vec) return -1;
+      return f(KTag<P, S, false, false, true>{});
+    }
   } else {
     switch (layout) {
       case LAYOUT_NN:
@@ -102,7 +111,8 @@ template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f)
     case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, f);
     case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, f);
     case CFG_128x256_W8:
-      if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3)
+      if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3 || P == PREC_FSPLIT ||
+                    P == PREC_FSPLIT3)
         return by_layout<P, S128x256w8>(layout, vec, f);
       else
         return -1;   // 16-bit only (the host never picks it)
@@ -117,6 +127,8 @@ template <class F> static int visit(int prec, int layout, int cfg, bool vec, F &
     case PREC_BF16: return by_cfg<PREC_BF16>(layout, cfg, vec, f);
     case PREC_SPLIT: return by_cfg<PREC_SPLIT>(layout, cfg, vec, f);
     case PREC_SPLIT3: return by_cfg<PREC_SPLIT3>(layout, cfg, vec, f);
+    case PREC_FSPLIT: return by_cfg<PREC_FSPLIT>(layout, cfg, vec, f);
+    case PREC_FSPLIT3: return by_cfg<PREC_FSPLIT3>(layout, cfg, vec, f);
   }
   return -1;
 }
@@ -136,6 +148,11 @@ int plain_occupancy(int prec, int layout, int cfg, bool vec) {
   };
   const int r = visit(prec, layout, cfg, vec, f);
   return r < 0 ? 0 : r;
+}
+
+bool plain_offered(int prec, int layout, int cfg, bool vec) {
+  auto f = []<int P, class S, bool TA, bool TB, bool VEC>(KTag<P, S, TA, TB, VEC>) -> int { return 0; };
+  return visit(prec, layout, cfg, vec, f) >= 0;
 }
 
 }  // namespace g355

@@ -14,19 +14,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gemm_tile.hpp"
 #include "internal.h"
 
 namespace g355 {
-
-template <int NP> __device__ __forceinline__ void split_x(float x, uint16_t (&o)[NP]) {
-  float r = x;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const __bf16 b = (__bf16)r;
-    o[p] = __builtin_bit_cast(uint16_t, b);
-    if (p + 1 < NP) r = r - (float)b;
-  }
-}
 
 // Plane pointers of one split operand.
 template <int NP> struct Planes { uint16_t *p[NP]; };
