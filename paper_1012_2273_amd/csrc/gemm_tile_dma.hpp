@@ -212,6 +212,15 @@ struct DmaOp {
     }
     return v;
   }
+
+  // MN layout: IL consecutive elements (M or N index `row`, a multiple of
+  // IL, IL dividing the 16-byte chunk) of K row k, one LDS read.
+  template <int IL>
+  __device__ __forceinline__ static VecT<E, IL> read_row(const char *region, int row, int k) {
+    static_assert(!KC && !TR && V % IL == 0, "MN rows of 4- or 8-byte elements");
+    return *reinterpret_cast<const VecT<E, IL> *>(region + k * RB + (((row / V) ^ swzm(k)) * 16) +
+                                                   (row % V) * ES);
+  }
 };
 
 // MFMA block geometry on this path: the 16-bit precisions use 32 x 32 x 16
@@ -327,6 +336,17 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   constexpr int RU = RU0 < KPL ? KPL : RU0;     // at least one MFMA operand
   constexpr int U = KW / RU, SPU = RU / KPL;
   constexpr int CV = T::CVT;
+  // MN-contiguous operands of the one-element-per-lane MFMAs (binary64,
+  // binary32): IL neighbouring 16-wide blocks take interleaved rows/columns
+  // (block g*IL + t, lane c: index 16*IL*g + IL*c + t), so that a lane's
+  // values for the IL blocks at one k are adjacent in LDS and come in one
+  // read (ds_read_b128 for IL * element size = 16) instead of IL. The
+  // epilogue maps the blocks back; every output element still receives the
+  // same MFMA sequence.
+  constexpr int ILA = (TA && KPL == 1 && !OA::TR) ? (VE < FM ? VE : FM) : 1;
+  constexpr int ILB = (!TB && KPL == 1 && !OB::TR) ? (VE < FN ? VE : FN) : 1;
+  static_assert(FM % ILA == 0 && FN % ILB == 0 && (ILA == 1 || MB == 16) && (ILB == 1 || MB == 16),
+                "interleave");
   constexpr int NB = FM * FN, NB1 = NB / 2;
   constexpr int STAGE = Plan::STAGE, DPW = Plan::PER_WAVE;
   constexpr int NS = Plan::NS, D = NS - 1;     // ring stages, transfer distance in tiles
@@ -376,12 +396,36 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     const int koff = lgp * KG + kh * KW + u * RU;
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
+      if constexpr (ILA > 1) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-        fa[b][pl][i] = OA::template read<RU>(regA(st, pl), wm * S::WTM + i * MB + lr, koff);
+        for (int g = 0; g < FM / ILA; ++g)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * MB + lr, koff);
+          for (int e = 0; e < RU; ++e) {
+            const auto v = OA::template read_row<ILA>(regA(st, pl), wm * S::WTM + g * 16 * ILA + ILA * lr,
+                                                      koff + e);
+#pragma unroll
+            for (int t = 0; t < ILA; ++t) fa[b][pl][g * ILA + t].e[e] = v.e[t];
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          fa[b][pl][i] = OA::template read<RU>(regA(st, pl), wm * S::WTM + i * MB + lr, koff);
+      }
+      if constexpr (ILB > 1) {
+#pragma unroll
+        for (int g = 0; g < FN / ILB; ++g)
+#pragma unroll
+          for (int e = 0; e < RU; ++e) {
+            const auto v = OB::template read_row<ILB>(regB(st, pl), wn * S::WTN + g * 16 * ILB + ILB * lr,
+                                                      koff + e);
+#pragma unroll
+            for (int t = 0; t < ILB; ++t) fb[b][pl][g * ILB + t].e[e] = v.e[t];
+          }
+      } else {
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          fb[b][pl][j] = OB::template read<RU>(regB(st, pl), wn * S::WTN + j * MB + lr, koff);
+      }
     }
   };
   auto op_of = [](const auto &u, int step) {
@@ -595,10 +639,11 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   for (int i = 0; i < FM; ++i) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int64_t col = n0 + wn * S::WTN + j * MB + lr;
+      const int64_t col = n0 + wn * S::WTN + (j / ILB) * MB * ILB + ILB * lr + j % ILB;
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
-        const int64_t row = m0 + wm * S::WTM + i * MB + (q / GRP) * LGN * GRP + lgp * GRP + q % GRP;
+        const int r = (q / GRP) * LGN * GRP + lgp * GRP + q % GRP;   // row within the block
+        const int64_t row = m0 + wm * S::WTM + (i / ILA) * MB * ILA + ILA * r + i % ILA;
         if (row < g.M && col < g.N) C[row * g.ldc + col] = (Out)acc[i][j][q];
       }
     }
