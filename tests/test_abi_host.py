@@ -75,6 +75,19 @@ def test_plain_validation(lib):
     assert _plain(lib, n=0, B=0, C=0, ldb=0, ldc=0) == _lib.GEMM_OK
 
 
+def test_split_one_launch_query_without_device(lib):
+    """Empty, null or misaligned operands report the two-step form (0)
+    before the library looks at the device."""
+    v = ctypes.c_void_p
+    assert lib.gemm_split_one_launch(0, 8, 8, v(256), 8, v(256), 8) == 0
+    assert lib.gemm_split_one_launch(8, 8, 8, None, 8, v(256), 8) == 0
+    assert lib.gemm_split_one_launch(8, 8, 8, v(256), 8, None, 8) == 0
+    assert lib.gemm_split_one_launch(8, 8, 8, v(260), 8, v(256), 8) == 0   # base not 16-byte aligned
+    assert lib.gemm_split_one_launch(8, 8, 8, v(256), 9, v(256), 8) == 0   # row pitch 36 bytes
+    assert lib.gemm_split_one_launch(8, 8, 6, v(256), 8, v(256), 8) == 0   # k not a multiple of 4
+    assert lib.gemm_split_one_launch(8, 8, 2048, v(256), 2048, v(256), 8) == 0   # long K loop
+
+
 def test_split_workspace_size(lib):
     assert lib.gemm_split_workspace_size(-1, 2, 2) == 0
     s = lib.gemm_split_workspace_size(2000, 2000, 2000)
