@@ -81,7 +81,7 @@ __device__ __forceinline__ void raw_barrier() {
 // One operand plane of one K-tile: R rows (M or N) x BK. LG: K rows
 // between the lane groups of one LDS read, MBW: lanes per lane group (the
 // MFMA block width; both set the MN layout swizzle).
-template <typename E, int R, int BK, int NT, bool KC, int LG, int MBW = 16>
+template <typename E, int R, int BK, int NT, bool KC, int LG, int MBW = 16, bool FLAT = false>
 struct DmaOp {
   static constexpr int ES = (int)sizeof(E);
   static constexpr int V = 16 / ES;                  // elements per chunk
@@ -109,12 +109,18 @@ struct DmaOp {
   // 4- and 8-byte elements: the 64 / MBW lane groups of a read take rows LG
   // apart, MBW consecutive elements each; moving row k's chunks by
   // (k / LG) % (64 / MBW) such spans puts the groups on different banks.
+  // FLAT: rows read 16 bytes per lane (the interleaved reads below), each
+  // lane group a whole 256-byte span: no swizzle (measured: ds_read_b128
+  // runs at full rate when lane groups 0/1 and 2/3 take their chunks in the
+  // same order, ~20% slower when group 1's order differs from group 0's).
   __device__ __forceinline__ static int swzm(int r) {
     if constexpr (KC) return 0;
     else if constexpr (TR) {
       if constexpr (CPR >= 8) return 2 * (r % 4);
       else if constexpr (CPR >= 4) return 2 * (r % 2);
       else return 0;
+    } else if constexpr (FLAT) {
+      return 0;
     } else {
       constexpr int NGR = 64 / MBW, SPAN = MBW * ES / 16;
       return (((r / LG) & (NGR - 1)) * SPAN) & (CPR - 1);
@@ -259,8 +265,20 @@ template <int DPW, int MAXT> __device__ __forceinline__ void wait_tiles(int n) {
 template <int P, class S, bool TA, bool TB> struct DmaPlan {
   using T = Traits<P>;
   using E = typename T::E;
-  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA, Geom<P, S>::KG, Geom<P, S>::MB>;
-  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB, Geom<P, S>::KG, Geom<P, S>::MB>;
+  // MN-contiguous operands of the one-element-per-lane MFMAs (binary64,
+  // binary32): IL neighbouring 16-wide blocks take interleaved rows/columns
+  // (block g*IL + t, lane c: index 16*IL*g + IL*c + t), so that a lane's
+  // values for the IL blocks at one k are adjacent in LDS and come in one
+  // read (ds_read_b128 for IL * element size = 16) instead of IL. The
+  // epilogue maps the blocks back; every output element still receives the
+  // same MFMA sequence.
+  static constexpr int ES = (int)sizeof(E), VE = 16 / ES;
+  static constexpr int ILA =
+      (TA && T::KPL == 1 && ES >= 4) ? (VE < Geom<P, S>::FM ? VE : Geom<P, S>::FM) : 1;
+  static constexpr int ILB =
+      (!TB && T::KPL == 1 && ES >= 4) ? (VE < Geom<P, S>::FN ? VE : Geom<P, S>::FN) : 1;
+  using OA = DmaOp<E, S::BM, bk_of<P, S>(), S::NT, !TA, Geom<P, S>::KG, Geom<P, S>::MB, ILA * ES == 16>;
+  using OB = DmaOp<E, S::BN, bk_of<P, S>(), S::NT, TB, Geom<P, S>::KG, Geom<P, S>::MB, ILB * ES == 16>;
   static constexpr int STAGE = T::PLANES * (OA::BYTES + OB::BYTES);
   static constexpr int PER_WAVE = T::PLANES * (OA::PERW + OB::PERW);   // transfers per tile
   // Ring depth: transfers run NS - 1 K-tiles ahead of the MFMAs. binary64
@@ -336,15 +354,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   constexpr int RU = RU0 < KPL ? KPL : RU0;     // at least one MFMA operand
   constexpr int U = KW / RU, SPU = RU / KPL;
   constexpr int CV = T::CVT;
-  // MN-contiguous operands of the one-element-per-lane MFMAs (binary64,
-  // binary32): IL neighbouring 16-wide blocks take interleaved rows/columns
-  // (block g*IL + t, lane c: index 16*IL*g + IL*c + t), so that a lane's
-  // values for the IL blocks at one k are adjacent in LDS and come in one
-  // read (ds_read_b128 for IL * element size = 16) instead of IL. The
-  // epilogue maps the blocks back; every output element still receives the
-  // same MFMA sequence.
-  constexpr int ILA = (TA && KPL == 1 && !OA::TR) ? (VE < FM ? VE : FM) : 1;
-  constexpr int ILB = (!TB && KPL == 1 && !OB::TR) ? (VE < FN ? VE : FN) : 1;
+  constexpr int ILA = Plan::ILA, ILB = Plan::ILB;   // interleaved MN blocks (DmaPlan)
   static_assert(FM % ILA == 0 && FN % ILB == 0 && (ILA == 1 || MB == 16) && (ILB == 1 || MB == 16),
                 "interleave");
   constexpr int NB = FM * FN, NB1 = NB / 2;
