@@ -73,19 +73,21 @@ static int device_cus() {
 // products N = 500 .. 8192, every shape forced in turn). The deciding
 // quantity is how many 128 x 128 tiles C has against the 256 CUs: with
 // fewer than ~48 smaller tiles are needed to occupy the CUs, up to ~200 the
-// medium shapes win, above that one 8-wave workgroup per CU (K split for
-// binary64, 128 x 64 K split for binary32, 8 waves for the 16-bit paths),
-// and from two tiles per CU on the shapes that keep two or more
-// workgroups per CU (4-wave 128 x 128 for binary64/binary32) or move fewer
-// operand bytes per flop (128 x 256 for the 16-bit paths).
+// medium shapes win, above that one 8-wave workgroup per CU (binary64: 4 x 2
+// waves of 32 x 64, 1.5% ahead of the K split at N = 1800 .. 3000; 128 x 64
+// K split for binary32, 8 waves for the 16-bit paths), and with more tiles
+// the shapes that keep two or more workgroups per CU (4-wave 128 x 128 for
+// binary64 once there is more than one tile per CU, ~2% ahead of the 8-wave
+// tile at N = 2500 and 2800; for binary32 from two tiles per CU) or move
+// fewer operand bytes per flop (128 x 256 for the 16-bit paths).
 static int choose_rule(int prec, int64_t m, int64_t n) {
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
   const int64_t cus = device_cus();
   const int64_t big = cus * 200 / 256, mid = cus * 48 / 256;
   switch (prec) {
     case PREC_F64:
-      if (t128 >= 2 * cus) return CFG_128x128;
-      if (t128 >= big) return CFG_128x128_K2;
+      if (t128 > cus) return CFG_128x128;
+      if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     case PREC_F32:
       if (t128 >= 2 * cus) return CFG_128x128;
@@ -123,15 +125,16 @@ static int occupancy(int prec, int layout, int cfg, bool vec) {
 static double shape_rate(int prec, int cfg) {
   if (prec == PREC_F64) {
     switch (cfg) {
-      case CFG_128x128: return 67.4;
-      case CFG_128x128_K2: return 65.6;
-      case CFG_64x64: return 61.3;
+      case CFG_128x128: return 69.2;
+      case CFG_128x128_W8: return 68.2;
+      case CFG_128x128_K2: return 67.4;
+      case CFG_64x64: return 62.2;
     }
   } else {
     switch (cfg) {
-      case CFG_128x128: return 134.0;
-      case CFG_128x64_K2: return 127.0;
-      case CFG_64x64_K2: return 119.6;
+      case CFG_128x128: return 136.6;
+      case CFG_128x64_K2: return 128.8;
+      case CFG_64x64_K2: return 122.2;
     }
   }
   return 0.0;
