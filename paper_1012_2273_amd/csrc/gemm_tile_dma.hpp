@@ -408,13 +408,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     for (int pl = 0; pl < PL; ++pl) {
       if constexpr (ILA > 1) {
 #pragma unroll
-        for (int g = 0; g < FM / ILA; ++g)
+        for (int gi = 0; gi < FM / ILA; ++gi)
 #pragma unroll
           for (int e = 0; e < RU; ++e) {
-            const auto v = OA::template read_row<ILA>(regA(st, pl), wm * S::WTM + g * 16 * ILA + ILA * lr,
-                                                      koff + e);
+            const auto v = OA::template read_row<ILA>(
+                regA(st, pl), wm * S::WTM + gi * MB * ILA + ILA * lr, koff + e);
 #pragma unroll
-            for (int t = 0; t < ILA; ++t) fa[b][pl][g * ILA + t].e[e] = v.e[t];
+            for (int t = 0; t < ILA; ++t) fa[b][pl][gi * ILA + t].e[e] = v.e[t];
           }
       } else {
 #pragma unroll
@@ -423,13 +423,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
       }
       if constexpr (ILB > 1) {
 #pragma unroll
-        for (int g = 0; g < FN / ILB; ++g)
+        for (int gi = 0; gi < FN / ILB; ++gi)
 #pragma unroll
           for (int e = 0; e < RU; ++e) {
-            const auto v = OB::template read_row<ILB>(regB(st, pl), wn * S::WTN + g * 16 * ILB + ILB * lr,
-                                                      koff + e);
+            const auto v = OB::template read_row<ILB>(
+                regB(st, pl), wn * S::WTN + gi * MB * ILB + ILB * lr, koff + e);
 #pragma unroll
-            for (int t = 0; t < ILB; ++t) fb[b][pl][g * ILB + t].e[e] = v.e[t];
+            for (int t = 0; t < ILB; ++t) fb[b][pl][gi * ILB + t].e[e] = v.e[t];
           }
       } else {
 #pragma unroll
