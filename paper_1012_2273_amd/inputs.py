@@ -13,6 +13,12 @@ without naming a distribution; the recipes here are:
   10^u, u ~ U(-3, 3), in binary64 before rounding to binary32 (row norms
   spread log-uniformly over 1e-3 .. 1e3).
 * ``batch_sizes``: N_i = rint(exp(U(ln 10, ln 2000))), clipped to [10, 2000].
+* ``hashed_integers``: integers -8..8 addressed by (row, column): entry (i, j)
+  is the SplitMix64 output function (Steele, Lea and Flood, 2014) of the
+  counter salt * 0x9E3779B97F4A7C15 + i * 2^32 + j, reduced mod 17 and
+  shifted by -8. Any set of rows or columns of an arbitrarily large matrix
+  can be regenerated without drawing the rest (used for operands of several
+  GiB whose sampled outputs are checked).
 
 Seeds: ``seed_for(cfg, n, variant)`` = 1_000_000*cfg + n (+500_000 for the
 variant); generator PCG64.
@@ -99,3 +105,27 @@ def special(kind: str, n: int, seed=0, dtype=np.float64):
     if kind == "diagonal":
         return np.diag(g.integers(-8, 8, size=n, endpoint=True).astype(dtype))
     raise ValueError(kind)
+
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _splitmix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on uint64 arrays (wrapping arithmetic)."""
+    z = z + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def hashed_integers(rows, cols, salt: int) -> np.ndarray:
+    """Entries (rows[a], cols[b]) of the addressable integer matrix of the
+    given salt (see the module docstring), as a len(rows) x len(cols)
+    float64 array; ``cols`` may be an int n for columns 0..n-1."""
+    r = np.asarray(rows, dtype=np.uint64).reshape(-1, 1)
+    c = (np.arange(cols, dtype=np.uint64) if np.isscalar(cols) else
+         np.asarray(cols, dtype=np.uint64)).reshape(1, -1)
+    with np.errstate(over="ignore"):
+        base = np.uint64(salt) * np.uint64(0x9E3779B97F4A7C15)
+        z = _splitmix64(base + (r << np.uint64(32)) + c)
+    return (z % np.uint64(17)).astype(np.int64).astype(np.float64) - 8.0
