@@ -105,7 +105,8 @@ struct DmaOp {
 
   __device__ __forceinline__ static int swz(int r) { return ((r * RB) >> 8) % CPR; }
   // MN rows. 16-bit elements: rows k .. k+3 of one transposing read put
-  // their 32-byte column blocks in four different 32-byte bank groups.
+  // their column blocks (32 bytes for 16-wide MFMA blocks, 64 for 32-wide)
+  // in four different bank groups.
   // 4- and 8-byte elements: the 64 / MBW lane groups of a read take rows LG
   // apart, MBW consecutive elements each; moving row k's chunks by
   // (k / LG) % (64 / MBW) such spans puts the groups on different banks.
@@ -116,7 +117,11 @@ struct DmaOp {
   __device__ __forceinline__ static int swzm(int r) {
     if constexpr (KC) return 0;
     else if constexpr (TR) {
-      if constexpr (CPR >= 8) return 2 * (r % 4);
+      // a half-wave's transposing read takes MBW columns (MBW * 2 bytes) of
+      // each of four rows: shift row k by (k % 4) such spans
+      constexpr int SPAN = MBW * ES / 16;
+      if constexpr (CPR >= 4 * SPAN) return SPAN * (r % 4);
+      else if constexpr (CPR >= 8) return 2 * (r % 4);
       else if constexpr (CPR >= 4) return 2 * (r % 2);
       else return 0;
     } else if constexpr (FLAT) {
