@@ -135,3 +135,22 @@ def test_fused_zero_k_and_empty(G):
         fn(A, B, C)
         torch.cuda.synchronize()
         assert int(torch.count_nonzero(C)) == 0
+
+
+@pytest.mark.parametrize("name", ["gemm_split", "gemm_split3"])
+def test_one_launch_leaves_workspace_untouched(G, name):
+    """The one-launch form needs no planes: the caller's workspace keeps its
+    contents; the two-step form writes its planes there."""
+    torch = _torch()
+    m, n, k = 96, 128, 200
+    A, B = inputs.uniform_mnk(m, n, k, 31, dtype=np.float32)
+    Ad, Bd = dev(A, torch), dev(B, torch)
+    size = getattr(G, name + "_workspace_size")(m, n, k)
+    ws = torch.full((size,), 0xA5, dtype=torch.uint8, device="cuda:0")
+    assert G.split_one_launch(Ad, Bd)
+    getattr(G, name)(Ad, Bd, None, ws)
+    torch.cuda.synchronize()
+    assert bool((ws == 0xA5).all())
+    getattr(G, name)(_pitched(A, torch), Bd, None, ws)
+    torch.cuda.synchronize()
+    assert not bool((ws == 0xA5).all())
