@@ -4,10 +4,11 @@
 // Algorithm 1, reduction blocked over K-tiles), different data movement:
 // operands go HBM/L2 -> LDS with `buffer_load_dwordx4 ... lds` (no VGPR
 // staging), into a ring of two to eight LDS stages, several K-tiles ahead
-// of the MFMAs. Waits are explicit: every wave issues the same number of 16-byte
-// transfers per K-tile, so `s_waitcnt vmcnt(n)` with n = one tile's count
-// retires exactly the tile about to be read; a barrier then makes all
-// waves' transfers visible.
+// of the MFMAs. Waits are explicit: every loader wave (all waves, or the first
+// half or quarter where a K-tile's transfers do not divide evenly) issues the
+// same number of 16-byte transfers per K-tile, so `s_waitcnt vmcnt(n)` with
+// n = one tile's count retires exactly the tile about to be read; a barrier
+// then makes all waves' transfers visible.
 //
 // LDS layouts (one transfer instruction fills 1 KiB: lane l -> base + 16 l):
 //  * K-contiguous operand (A not transposed, B transposed): rows of BK

@@ -16,8 +16,9 @@ struct GemmArgs;
 // value the tuner and the grouped planner store. The K-split ones (512 threads: two waves per output
 // position, each taking half of every K-tile) are the ones the persistent
 // grouped kernel offers; every configuration runs as a single product.
-// The last one is 16-bit only: 128x256w8 (8 waves of 64 x 64 outputs with
-// 32-deep K-tiles, 25% fewer operand bytes per flop than 128 x 128).
+// The last one is offered to the bfloat16-MFMA products only: 128x256w8 (8
+// waves of 64 x 64 outputs with 32-deep K-tiles, 25% fewer operand bytes per
+// flop than 128 x 128).
 enum TileCfg : int {
   CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3,
   CFG_128x128_W8 = 4, CFG_128x128_K2 = 5, CFG_128x64_K2 = 6, CFG_64x64_K2 = 7,

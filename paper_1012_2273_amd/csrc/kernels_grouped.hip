@@ -39,7 +39,8 @@ template <int P> __host__ __device__ constexpr int grouped_lds() {
 }
 
 // Same path choice as a single launch: direct-to-LDS when the operands allow
-// 16-byte transfers and the shape splits evenly into them, else registers.
+// 16-byte transfers and the shape's K-tile splits into whole 1 KiB transfers
+// per loader wave, else registers.
 // Problems with and without 16-byte operands go to two kernels (VEC), which
 // keeps each kernel's register allocation to the paths it runs.
 template <int P, class S, bool VEC>

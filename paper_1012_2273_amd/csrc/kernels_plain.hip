@@ -115,7 +115,7 @@ template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f)
                     P == PREC_FSPLIT3)
         return by_layout<P, S128x256w8>(layout, vec, f);
       else
-        return -1;   // 16-bit only (the host never picks it)
+        return -1;   // bfloat16-MFMA products only (the host never picks it)
   }
   return -1;
 }
