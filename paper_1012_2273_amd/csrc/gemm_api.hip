@@ -33,7 +33,8 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
                                          {64, 64, "64x64"},     {32, 32, "32x32"},
                                          {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
                                          {128, 64, "128x64k2"},   {64, 64, "64x64k2"},
-                                         {32, 32, "32x32k2"},     {128, 256, "128x256w8"}};
+                                         {32, 32, "32x32k2"},     {128, 256, "128x256w8"},
+                                         {64, 64, "64x64k4"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
@@ -45,6 +46,7 @@ bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
+  if (cfg == CFG_64x64_K4) return prec == PREC_F64;
   return true;
 }
 bool cfg_grouped(int cfg) {
@@ -73,7 +75,10 @@ static int device_cus() {
 // products N = 500 .. 8192, every shape forced in turn). The deciding
 // quantity is how many 128 x 128 tiles C has against the 256 CUs: with
 // fewer than ~48 smaller tiles are needed to occupy the CUs, up to ~200 the
-// medium shapes win, above that one 8-wave workgroup per CU (binary64: 4 x 2
+// medium shapes win (binary64 up to ~80: one 16-wave 64 x 64 workgroup per
+// CU with K split four ways, 41.8 against 37.5 TFLOP/s for the 4-wave tile at
+// N = 1000, 27.1 against 24.4 at N = 800, behind it from N = 1200), above
+// that one 8-wave workgroup per CU (binary64: 4 x 2
 // waves of 32 x 64, 1.5% ahead of the K split at N = 1800 .. 3000; 128 x 64
 // K split for binary32, 8 waves for the 16-bit paths), and with more tiles
 // the shapes that keep two or more workgroups per CU (4-wave 128 x 128 for
@@ -88,7 +93,15 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
     case PREC_F64:
       if (t128 > cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x128_W8;
-      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+      if (t128 >= mid) {
+        if (t128 <= cus * 80 / 256) return CFG_64x64_K4;
+        // 324..361 tiles of 64 x 64 leave a fifth to two fifths of the CUs
+        // with a second tile; 32 x 32 tiles spread evenly (N = 1100: 36.3
+        // against 30.5 TFLOP/s, N = 1200: 38.3 against 36.5; 64 x 64 again
+        // ahead from N = 1300, 41.9 against 37.4)
+        return t128 <= cus * 110 / 256 ? CFG_32x32 : CFG_64x64;
+      }
+      return CFG_32x32;
     case PREC_F32:
       if (t128 >= 2 * cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x64_K2;

@@ -97,6 +97,7 @@ using S128x128k2 = Shape<128, 128, 2, 2, 2>;
 using S128x64k2 = Shape<128, 64, 2, 2, 2>;
 using S64x64k2 = Shape<64, 64, 2, 2, 2>;
 using S32x32k2 = Shape<32, 32, 2, 2, 2>;
+using S64x64k4 = Shape<64, 64, 2, 2, 4, 32>;   // 1024 threads
 using S128x256w8 = Shape<128, 256, 2, 4, 1, 32>;
 
 template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f) {
@@ -110,6 +111,11 @@ template <int P, class F> static int by_cfg(int layout, int cfg, bool vec, F &f)
     case CFG_128x64_K2: return by_layout<P, S128x64k2>(layout, vec, f);
     case CFG_64x64_K2: return by_layout<P, S64x64k2>(layout, vec, f);
     case CFG_32x32_K2: return by_layout<P, S32x32k2>(layout, vec, f);
+    case CFG_64x64_K4:
+      if constexpr (P == PREC_F64)
+        return by_layout<P, S64x64k4>(layout, vec, f);
+      else
+        return -1;   // binary64 only (the host never picks it)
     case CFG_128x256_W8:
       if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3 || P == PREC_FSPLIT ||
                     P == PREC_FSPLIT3)
