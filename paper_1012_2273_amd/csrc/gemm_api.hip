@@ -73,18 +73,20 @@ static int device_cus() {
 
 // Tile shape for one product, from measured sweeps on MI355X (square
 // products N = 500 .. 8192, every shape forced in turn). The deciding
-// quantity is how many 128 x 128 tiles C has against the 256 CUs: with
-// fewer than ~48 smaller tiles are needed to occupy the CUs, up to ~200 the
-// medium shapes win (binary64 up to ~80: one 16-wave 64 x 64 workgroup per
-// CU with K split four ways, 41.8 against 37.5 TFLOP/s for the 4-wave tile at
-// N = 1000, 27.1 against 24.4 at N = 800, behind it from N = 1200), above
-// that one 8-wave workgroup per CU (binary64: 4 x 2
-// waves of 32 x 64, 1.5% ahead of the K split at N = 1800 .. 3000; 128 x 64
-// K split for binary32, 8 waves for the 16-bit paths), and with more tiles
-// the shapes that keep two or more workgroups per CU (4-wave 128 x 128 for
-// binary64 once there is more than one tile per CU, ~2% ahead of the 8-wave
-// tile at N = 2500 and 2800; for binary32 from two tiles per CU) or move
-// fewer operand bytes per flop (128 x 256 for the 16-bit paths).
+// quantity is the number t of 128 x 128 tiles of C against the 256 CUs:
+//  * fewer than ~48: small tiles occupy the CUs;
+//  * up to ~200: medium shapes. binary64: one 16-wave 64 x 64 workgroup per
+//    CU with K split four ways up to ~80 (N = 1000: 41.8 against 37.5
+//    TFLOP/s for the 4-wave tile, N = 800: 27.1 against 24.4), 32 x 32 up
+//    to ~110 (below), 64 x 64 above;
+//  * up to one tile per CU: one 8-wave workgroup per CU (binary64: 4 x 2
+//    waves of 32 x 64, 1.5% ahead of the K split at N = 1800 .. 3000;
+//    binary32: 128 x 64 K split; 16-bit: 128 x 128 with 8 waves);
+//  * more: binary64/binary32 the 4-wave 128 x 128 tile, two workgroups per
+//    CU (binary64 ~2% ahead of the 8-wave tile at N = 2500 and 2800,
+//    binary32 91.6 -> 98.6 and 115.6 -> 123.9 TFLOP/s against the 128 x 64
+//    K split there); 16-bit from two tiles per CU the 128 x 256 tile, which
+//    moves fewer operand bytes per flop.
 static int choose_rule(int prec, int64_t m, int64_t n) {
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
   const int64_t cus = device_cus();
@@ -103,7 +105,7 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
       }
       return CFG_32x32;
     case PREC_F32:
-      if (t128 >= 2 * cus) return CFG_128x128;
+      if (t128 > cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x64_K2;
       return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
     case PREC_BF16:
