@@ -157,13 +157,16 @@ static double shape_rate(int prec, int cfg) {
 
 // Time estimate of a shape in whole rounds of the device's workgroup slots:
 // rounds x (tiles a CU holds per round x tile area) / large-N rate.
-static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int64_t n) {
+// whole = false counts the last round by how full it is (freed slots take
+// the next tiles as workgroups finish).
+static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int64_t n,
+                         bool whole = true) {
   const int bm = kCfgs[cfg].bm, bn = kCfgs[cfg].bn;
   const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
   const int occ = occupancy(prec, layout, cfg, vec);
   const int64_t slots = (int64_t)device_cus() * occ;
-  const int64_t rounds = (tiles + slots - 1) / slots;
-  return (double)rounds * occ * bm * bn / shape_rate(prec, cfg);
+  const double rounds = whole ? (double)((tiles + slots - 1) / slots) : (double)tiles / slots;
+  return rounds * occ * bm * bn / shape_rate(prec, cfg);
 }
 
 // The rule above ignores how full the last round of workgroups is: at
@@ -182,7 +185,14 @@ static int choose_cfg(int prec, int layout, bool vec, int64_t m, int64_t n) {
   if (kCfgs[pick].bm < 128 || shape_rate(prec, pick) <= 0.0) return pick;
   const double cp = round_cost(prec, layout, vec, pick, m, n);
   const double ca = round_cost(prec, layout, vec, alt, m, n);
-  return ca < 0.85 * cp ? alt : pick;
+  if (ca < 0.85 * cp) return alt;
+  // the 64 x 64 shapes hold several workgroups per CU, so their last round fills
+  // as slots free up: compare its fractional rounds too (N = 3600: 3249 tiles
+  // of 64 x 64 over 768 slots against 841 of 128 x 128 over 512; binary64
+  // 58.1 against 53.2 TFLOP/s, binary32 113.1 against 104.2), unless whole
+  // rounds make it clearly slower (N = 2500: 3 rounds against 1, a 1% loss)
+  const double caf = round_cost(prec, layout, vec, alt, m, n, false);
+  return caf < 0.90 * cp && ca < 1.10 * cp ? alt : pick;
 }
 
 static size_t esize_of(int dtype) {
