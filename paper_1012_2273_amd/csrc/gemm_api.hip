@@ -120,16 +120,16 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
 }
 
 // Workgroups one CU holds for a kernel, cached per device.
-static int occupancy(int prec, int layout, int cfg, bool vec) {
+static int occupancy(int prec, int layout, int cfg, int vw) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, int, int, int>, int> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
-  const auto key = std::make_tuple(dev, prec, layout, cfg, vec ? 1 : 0);
+  const auto key = std::make_tuple(dev, prec, layout, cfg, vw);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  int occ = plain_occupancy(prec, layout, cfg, vec);
+  int occ = plain_occupancy(prec, layout, cfg, vw);
   if (occ <= 0) occ = 1;
   cache[key] = occ;
   return occ;
@@ -159,11 +159,11 @@ static double shape_rate(int prec, int cfg) {
 // rounds x (tiles a CU holds per round x tile area) / large-N rate.
 // whole = false counts the last round by how full it is (freed slots take
 // the next tiles as workgroups finish).
-static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int64_t n,
+static double round_cost(int prec, int layout, int vw, int cfg, int64_t m, int64_t n,
                          bool whole = true) {
   const int bm = kCfgs[cfg].bm, bn = kCfgs[cfg].bn;
   const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
-  const int occ = occupancy(prec, layout, cfg, vec);
+  const int occ = occupancy(prec, layout, cfg, vw);
   const int64_t slots = (int64_t)device_cus() * occ;
   const double rounds = whole ? (double)((tiles + slots - 1) / slots) : (double)tiles / slots;
   return rounds * occ * bm * bn / shape_rate(prec, cfg);
@@ -174,24 +174,24 @@ static double round_cost(int prec, int layout, bool vec, int cfg, int64_t m, int
 // (46 TFLOP/s) where 2209 tiles of 64 x 64 fill three rounds of 768 (57).
 // binary64/binary32 step down to the 64 x 64 shape when the round count
 // says it is at least 15% faster.
-static int choose_cfg(int prec, int layout, bool vec, int64_t m, int64_t n) {
+static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   const int forced = g_force_cfg.load();
   if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced) &&
-      plain_offered(prec, layout, forced, vec))
+      plain_offered(prec, layout, forced, vw))
     return forced;
   const int pick = choose_rule(prec, m, n);
   if (prec != PREC_F64 && prec != PREC_F32) return pick;
   const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
   if (kCfgs[pick].bm < 128 || shape_rate(prec, pick) <= 0.0) return pick;
-  const double cp = round_cost(prec, layout, vec, pick, m, n);
-  const double ca = round_cost(prec, layout, vec, alt, m, n);
+  const double cp = round_cost(prec, layout, vw, pick, m, n);
+  const double ca = round_cost(prec, layout, vw, alt, m, n);
   if (ca < 0.85 * cp) return alt;
   // the 64 x 64 shapes hold several workgroups per CU, so their last round fills
   // as slots free up: compare its fractional rounds too (N = 3600: 3249 tiles
   // of 64 x 64 over 768 slots against 841 of 128 x 128 over 512; binary64
   // 58.1 against 53.2 TFLOP/s, binary32 113.1 against 104.2), unless whole
   // rounds make it clearly slower (N = 2500: 3 rounds against 1, a 1% loss)
-  const double caf = round_cost(prec, layout, vec, alt, m, n, false);
+  const double caf = round_cost(prec, layout, vw, alt, m, n, false);
   return caf < 0.90 * cp && ca < 1.10 * cp ? alt : pick;
 }
 
@@ -204,12 +204,13 @@ static size_t esize_of(int dtype) {
   return 0;
 }
 
-// 16-byte vector loads need an aligned base and row pitch, and a contiguous
-// extent that is a whole number of vectors (every vector is then entirely
-// inside or outside the matrix).
-static bool vec_ok(const void *p, int64_t ld, size_t es, int64_t contiguous_extent) {
-  const int64_t v = 16 / (int64_t)es;
-  return ((uintptr_t)p % 16 == 0) && (((uint64_t)ld * es) % 16 == 0) &&
+// Vector loads of `bytes` (16 or 8) need an aligned base and row pitch, and
+// a contiguous extent that is a whole number of vectors (every vector is
+// then entirely inside or outside the matrix).
+static bool vec_ok(const void *p, int64_t ld, size_t es, int64_t contiguous_extent,
+                   int bytes = 16) {
+  const int64_t v = bytes / (int64_t)es;
+  return v >= 1 && ((uintptr_t)p % bytes == 0) && (((uint64_t)ld * es) % bytes == 0) &&
          (contiguous_extent % v == 0);
 }
 
@@ -244,10 +245,18 @@ static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hi
   if ((rc = check_ld_range("A", a.lda, es_in)) || (rc = check_ld_range("B", a.ldb, es_in)))
     return rc;
   const bool ta = layout == LAYOUT_TN, tb = layout == LAYOUT_NT;
-  bool vec = vec_ok(a.A, a.lda, es_in, ta ? a.M : a.K) && vec_ok(a.B, a.ldb, es_in, tb ? a.K : a.N);
-  if (prec == PREC_SPLIT || prec == PREC_SPLIT3) vec = true;   // planes are padded to whole vectors
-  const int cfg = choose_cfg(prec, layout, vec, a.M, a.N);
-  hipError_t e = launch_plain(prec, layout, cfg, vec, a, s);
+  const int64_t ea = ta ? a.M : a.K, eb = tb ? a.K : a.N;   // contiguous extents
+  // widest vector loads both operands allow: 16 bytes (direct-to-LDS when the
+  // shape offers it), 8 bytes (register path; 2- and 4-byte elements), else
+  // single elements
+  int vw = 0;
+  if (vec_ok(a.A, a.lda, es_in, ea) && vec_ok(a.B, a.ldb, es_in, eb))
+    vw = 16;
+  else if (es_in < 8 && vec_ok(a.A, a.lda, es_in, ea, 8) && vec_ok(a.B, a.ldb, es_in, eb, 8))
+    vw = 8;
+  if (prec == PREC_SPLIT || prec == PREC_SPLIT3) vw = 16;   // planes are padded to whole vectors
+  const int cfg = choose_cfg(prec, layout, vw, a.M, a.N);
+  hipError_t e = launch_plain(prec, layout, cfg, vw, a, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return GEMM_OK;
 }

@@ -238,16 +238,17 @@ __device__ __forceinline__ typename RawT<BYTES>::T raw_load(__amdgpu_buffer_rsrc
 // Global -> VGPR -> LDS mover for one operand plane of R rows x BK.
 //   KC = true : element (r, p) at base[(r0 + r) * ld + k0 + p]
 //   KC = false: element (r, p) at base[(k0 + p) * ld + r0 + r]
-// Each thread moves whole vectors of V elements along the contiguous
-// direction. The host enables V > 1 only when every vector is entirely
-// inside or entirely outside the matrix (16-byte aligned base and ld, and the
-// contiguous extent a multiple of V); an outside vector gets the offset kOob
+// Each thread moves whole vectors of V = VW / sizeof(E) elements (VW = 16 or
+// 8 bytes; one element for VW = 0) along the contiguous direction. The host
+// enables V > 1 only when every vector is entirely inside or entirely outside
+// the matrix (VW-byte aligned base and ld, and the contiguous extent a
+// multiple of V); an outside vector gets the offset kOob
 // and the buffer unit returns zeros, so the tile edges need no branches.
 // Offsets are 32-bit byte offsets from the K-tile's base: R * ld * sizeof(E)
 // must stay below 2^31 (the host checks).
-template <typename E, int R, int BK, int NT, bool KC, bool VEC>
+template <typename E, int R, int BK, int NT, bool KC, int VW>
 struct Mover {
-  static constexpr int V = VEC ? 16 / (int)sizeof(E) : 1;
+  static constexpr int V = VW > (int)sizeof(E) ? VW / (int)sizeof(E) : 1;
   static constexpr int NVEC = R * BK / V;
   static constexpr int PER = (NVEC + NT - 1) / NT;
   static constexpr bool FULL = (NVEC % NT) == 0;
@@ -306,7 +307,8 @@ struct Mover {
 };
 
 // Compute one BM x BN tile of C at (m0, n0). TA: op(A) = A^T (A stored
-// K x M); TB: op(B) = B^T (B stored N x K). VEC: 16-byte loads allowed.
+// K x M); TB: op(B) = B^T (B stored N x K). VW: vector loads of VW bytes
+// allowed (16 or 8; 0: element loads).
 //
 // Schedule of one K-tile for one wave (U read units of the wave's K range):
 //   issue global loads of K-tile t+1 into VGPRs
@@ -316,7 +318,7 @@ struct Mover {
 //   MFMAs of the second half of the last unit's blocks
 // so the global-load latency is covered by the MFMAs before the store, and
 // the barrier and the first LDS reads of the next tile by the last half.
-template <int P, class S, bool TA, bool TB, bool VEC>
+template <int P, class S, bool TA, bool TB, int VW>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t n0,
                                           char *smem) {
   using T = Traits<P>;
@@ -350,8 +352,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int64_t m0, int64_t
   const E *Bp[3] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2),
                     reinterpret_cast<const E *>(g.B3)};
 
-  Mover<E, S::BM, BK, NT, !TA, VEC> ma[PL];
-  Mover<E, S::BN, BK, NT, TB, VEC> mb[PL];
+  // 8-byte vectors only along K: an MN-contiguous vector is stored to the
+  // K-major LDS tile one element per row, and four rows per lane put 16
+  // lanes of a 2-byte store on one bank (bf16 N = 4300: 164 against 296
+  // TFLOP/s with element loads)
+  constexpr int VWA = (VW == 8 && TA) ? 0 : VW, VWB = (VW == 8 && !TB) ? 0 : VW;
+  Mover<E, S::BM, BK, NT, !TA, VWA> ma[PL];
+  Mover<E, S::BN, BK, NT, TB, VWB> mb[PL];
 
   Acc acc[S::FM][S::FN];
 #pragma unroll

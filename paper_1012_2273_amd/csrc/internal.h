@@ -37,12 +37,12 @@ enum Layout : int { LAYOUT_NN = 0, LAYOUT_NT = 1, LAYOUT_TN = 2 };
 
 // Launch one single-product kernel (grid = all tiles of C).
 // prec: a Prec value (gemm_tile.hpp). Returns hipSuccess or the launch error.
-hipError_t launch_plain(int prec, int layout, int cfg, bool vec, const GemmArgs &a,
+hipError_t launch_plain(int prec, int layout, int cfg, int vw, const GemmArgs &a,
                         hipStream_t stream);
 // Workgroups of that kernel one CU holds at once (0 if not offered or unknown).
-int plain_occupancy(int prec, int layout, int cfg, bool vec);
+int plain_occupancy(int prec, int layout, int cfg, int vw);
 // Whether a kernel exists for that combination.
-bool plain_offered(int prec, int layout, int cfg, bool vec);
+bool plain_offered(int prec, int layout, int cfg, int vw);
 
 // Split kernels (np = 2: hi, lo; np = 3: hi, mid, lo). X (rows x cols, ldx)
 // -> np 16-bit planes. Plane rows are written up to `out_pad` >= their

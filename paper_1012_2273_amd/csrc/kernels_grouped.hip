@@ -49,7 +49,7 @@ __device__ __forceinline__ void run_item(const GemmArgs &g, const WorkItem &w, c
   if constexpr (VEC && dma_ok<P, S, false, false>())
     gemm_tile_dma<P, S, false, false>(g, m0, n0, smem);
   else
-    gemm_tile<P, S, false, false, VEC>(g, m0, n0, smem);
+    gemm_tile<P, S, false, false, VEC ? 16 : 0>(g, m0, n0, smem);
 }
 
 template <int P, bool VEC>
