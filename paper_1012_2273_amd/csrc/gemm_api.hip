@@ -136,11 +136,13 @@ static int occupancy(int prec, int layout, int cfg, int vw) {
 }
 
 // Large-N rate (TFLOP/s, square NN products N = 4096-8192 on MI355X) of the
-// binary64/binary32 shapes the round-count check compares.
+// binary64/binary32 shapes the round-count check compares (binary64 128 x 64:
+// about 0.93 of 128 x 128, its ratio at N = 6000).
 static double shape_rate(int prec, int cfg) {
   if (prec == PREC_F64) {
     switch (cfg) {
       case CFG_128x128: return 69.2;
+      case CFG_128x64: return 64.5;
       case CFG_128x128_W8: return 68.2;
       case CFG_128x128_K2: return 67.4;
       case CFG_64x64: return 62.2;
@@ -157,15 +159,23 @@ static double shape_rate(int prec, int cfg) {
 
 // Time estimate of a shape in whole rounds of the device's workgroup slots:
 // rounds x (tiles a CU holds per round x tile area) / large-N rate.
-// whole = false counts the last round by how full it is (freed slots take
-// the next tiles as workgroups finish).
+// Round counting: WHOLE counts every started round in full; FRACTION counts
+// the last round by how full it is (freed slots take the next tiles as
+// workgroups finish); ALONE counts a last round that gives each CU at most
+// one workgroup as half a round (a workgroup alone on a CU runs about twice
+// as fast as one sharing it).
+enum RoundCount { WHOLE, FRACTION, ALONE };
 static double round_cost(int prec, int layout, int vw, int cfg, int64_t m, int64_t n,
-                         bool whole = true) {
+                         RoundCount mode = WHOLE) {
   const int bm = kCfgs[cfg].bm, bn = kCfgs[cfg].bn;
   const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
   const int occ = occupancy(prec, layout, cfg, vw);
-  const int64_t slots = (int64_t)device_cus() * occ;
-  const double rounds = whole ? (double)((tiles + slots - 1) / slots) : (double)tiles / slots;
+  const int64_t cus = device_cus(), slots = cus * occ;
+  const int64_t full = tiles / slots, last = tiles - full * slots;
+  double rounds;
+  if (mode == FRACTION) rounds = (double)tiles / slots;
+  else if (mode == ALONE && last > 0 && last <= cus) rounds = full + 0.55;
+  else rounds = (double)(full + (last > 0 ? 1 : 0));
   return rounds * occ * bm * bn / shape_rate(prec, cfg);
 }
 
@@ -186,13 +196,25 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   const double cp = round_cost(prec, layout, vw, pick, m, n);
   const double ca = round_cost(prec, layout, vw, alt, m, n);
   if (ca < 0.85 * cp) return alt;
-  // the 64 x 64 shapes hold several workgroups per CU, so their last round fills
-  // as slots free up: compare its fractional rounds too (N = 3600: 3249 tiles
-  // of 64 x 64 over 768 slots against 841 of 128 x 128 over 512; binary64
-  // 58.1 against 53.2 TFLOP/s, binary32 113.1 against 104.2), unless whole
-  // rounds make it clearly slower (N = 2500: 3 rounds against 1, a 1% loss)
-  const double caf = round_cost(prec, layout, vw, alt, m, n, false);
-  return caf < 0.90 * cp && ca < 1.10 * cp ? alt : pick;
+  // The 64 x 64 shapes hold several workgroups per CU, so their last round
+  // fills as slots free up: compare their fractional rounds too (N = 3600:
+  // 3249 tiles of 64 x 64 over 768 slots against 841 of 128 x 128 over 512;
+  // binary64 58.1 against 53.2 TFLOP/s, binary32 113.1 against 104.2), unless
+  // whole rounds make them clearly slower (N = 2500: 3 rounds against 1, a 1%
+  // loss). A last round of the large shape that leaves each CU at most one
+  // workgroup runs at about twice the rate and counts as half a round
+  // (N = 4300: 132 such tiles; binary64 59.8 with 128 x 128 against 56.3
+  // with 64 x 64, binary32 117.9 against 110.7).
+  const double cph = round_cost(prec, layout, vw, pick, m, n, ALONE);
+  const double caf = round_cost(prec, layout, vw, alt, m, n, FRACTION);
+  if (caf < 0.90 * cph && ca < 1.10 * cp) return alt;
+  // binary64 also weighs 128 x 64 against 128 x 128 (N = 4500: 1296 tiles of
+  // 128 x 128 fill a third round of 512 slots only to 272; 128 x 64 gives
+  // 60.0 TFLOP/s against 55.1)
+  if (prec == PREC_F64 && pick == CFG_128x128 &&
+      round_cost(prec, layout, vw, CFG_128x64, m, n, ALONE) < 0.90 * cph)
+    return CFG_128x64;
+  return pick;
 }
 
 static size_t esize_of(int dtype) {
