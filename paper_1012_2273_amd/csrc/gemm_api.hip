@@ -208,12 +208,13 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   const double cph = round_cost(prec, layout, vw, pick, m, n, ALONE);
   const double caf = round_cost(prec, layout, vw, alt, m, n, FRACTION);
   if (caf < 0.90 * cph && ca < 1.10 * cp) return alt;
-  // binary64 also weighs 128 x 64 against 128 x 128 (N = 4500: 1296 tiles of
-  // 128 x 128 fill a third round of 512 slots only to 272; 128 x 64 gives
-  // 60.0 TFLOP/s against 55.1)
-  if (prec == PREC_F64 && pick == CFG_128x128 &&
-      round_cost(prec, layout, vw, CFG_128x64, m, n, ALONE) < 0.90 * cph)
-    return CFG_128x64;
+  // A 128 x 128 pick is also weighed against the 128 x 64 shape (N = 4500:
+  // 1296 tiles of 128 x 128 fill a third round of 512 slots only to 272;
+  // 128 x 64 gives binary64 60.0 TFLOP/s against 55.1, its K split binary32
+  // 122.5 against 108.9)
+  const int mid = prec == PREC_F64 ? CFG_128x64 : CFG_128x64_K2;
+  if (pick == CFG_128x128 && round_cost(prec, layout, vw, mid, m, n, ALONE) < 0.90 * cph)
+    return mid;
   return pick;
 }
 
