@@ -167,35 +167,55 @@ RECT_SHAPES = [(2000, 1000, 3000), (3000, 3000, 3000), (8192, 512, 8192), (512, 
                (4096, 4096, 512), (256, 256, 65536)]
 
 
+def _median_call_ms(fn, torch, stream):
+    """Median per-call time of fn() after >= 30 ms of warm-up, HIP events
+    on the stream the kernels run on."""
+    t_end = time.perf_counter() + 0.03
+    while True:
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() >= t_end:
+            break
+    pairs = []
+    for _ in range(10):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        pairs.append((e0, e1))
+    torch.cuda.synchronize()
+    return _median_ms(pairs)
+
+
 def rect_sweep(G, torch, dev, stream, inputs, check):
     """Rectangular binary64 products (m x k times k x n, the paper's problem
-    statement), median per-call rate after >= 30 ms of warm-up."""
+    statement), median per-call rate after >= 30 ms of warm-up; where
+    gemm_plain_ksplit splits the K loop (too few output tiles for the
+    device), its rate beside it ("ksplit")."""
     out = {}
     for m, n, k in RECT_SHAPES:
         A, B = inputs.uniform_mnk(m, n, k, 5_000_000 + m + n + k)
         Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
         Cd = torch.empty((m, n), dtype=torch.float64, device=dev)
-        t_end = time.perf_counter() + 0.03
-        while True:
-            for _ in range(3):
-                G.gemm_plain(Ad, Bd, Cd)
-            torch.cuda.synchronize()
-            if time.perf_counter() >= t_end:
-                break
-        pairs = []
-        for _ in range(10):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            G.gemm_plain(Ad, Bd, Cd)
-            e1.record(stream)
-            pairs.append((e0, e1))
-        torch.cuda.synchronize()
-        t = _median_ms(pairs) * 1e-3
+        t = _median_call_ms(lambda: G.gemm_plain(Ad, Bd, Cd), torch, stream) * 1e-3
         d = {"ms": round(t * 1e3, 5), "gflops": round(2.0 * m * n * k / t / 1e9, 2),
              "frac_peak": round(2.0 * m * n * k / t / 1e12 / PEAK["f64"], 4)}
+        ref = _blas(A, B) if check else None
         if check:
-            d["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), _blas(A, B)):.3e}")
+            d["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), ref):.3e}")
+        need = G.gemm_plain_ksplit_workspace_size(G.GEMM_F64, m, n, k)
+        if need > 0:
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            tk = _median_call_ms(lambda: G.gemm_plain_ksplit(Ad, Bd, Cd, ws), torch, stream) * 1e-3
+            ks = {"ms": round(tk * 1e3, 5), "gflops": round(2.0 * m * n * k / tk / 1e9, 2),
+                  "frac_peak": round(2.0 * m * n * k / tk / 1e12 / PEAK["f64"], 4),
+                  "workspace_bytes": need}
+            if check:
+                ks["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), ref):.3e}")
+            d["ksplit"] = ks
+            del ws
         out[f"{m}x{n}x{k}"] = d
         del Ad, Bd, Cd
     return out

@@ -75,6 +75,48 @@ int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k,
                void *C, int64_t ldc, void *stream);
 
 /*
+ * gemm_plain_ksplit_workspace_size -- bytes of device workspace
+ * gemm_plain_ksplit needs for this product: (chunks - 1) * m * n output
+ * elements (C's type), 0 when the product runs unsplit. Depends on the
+ * sizes, the device's CU count and the forced settings below only.
+ * Returns 0 for an unknown dtype or a size <= 0.
+ */
+size_t gemm_plain_ksplit_workspace_size(int dtype, int64_t m, int64_t n, int64_t k);
+
+/*
+ * gemm_plain_ksplit -- the product of gemm_plain (Section 3.1, Algorithm 1;
+ * same arguments and result type) for products with too few output tiles
+ * to occupy the device (mid-size squares, short and wide or long-K shapes):
+ * the sum over K is cut into chunks of whole K-tiles that run as separate
+ * workgroups of one launch, chunk 0 writing its partial product to C and
+ * chunk j > 0 to plane j - 1 of the workspace; a second launch adds the
+ * planes to C in chunk order. The association of the sum over K differs
+ * from gemm_plain's (one partial sum per chunk), the result is the same for
+ * every call with the same sizes on the same device. Products with enough
+ * tiles run as gemm_plain and leave the workspace untouched.
+ *   workspace, workspace_bytes  device memory owned by the caller, 16-byte
+ *     aligned, at least gemm_plain_ksplit_workspace_size(dtype, m, n, k)
+ *     bytes (NULL with 0 allowed when that is 0); its contents on entry do
+ *     not matter and are overwritten. Calls that share a workspace must be
+ *     ordered (one stream, or synchronised).
+ * Errors: those of gemm_plain, and EWORKSPACE (NULL, too small or not
+ * 16-byte aligned workspace).
+ */
+int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k,
+                      const void *A, int64_t lda, const void *B, int64_t ldb,
+                      void *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/*
+ * gemm_plain_ksplit_force -- make gemm_plain_ksplit cut K into `parts`
+ * chunks of a multiple of 64 indices each (fewer if K is short; -1 restores
+ * the automatic count). The tile shape follows gemm_plain_force_config when
+ * that names 128x128, 128x128w8, 128x64 or 64x64. For tests and tuning.
+ * Errors: EINVAL (parts 0, below -1 or above 65535).
+ */
+int gemm_plain_ksplit_force(int parts);
+
+/*
  * gemm_split_workspace_size -- bytes of device workspace gemm_split needs
  * for this shape (the four bfloat16 operand planes, rows of k rounded up to
  * 8 elements at a pitch rounded up to 64 elements, planes 256-byte aligned).

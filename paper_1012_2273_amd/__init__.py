@@ -23,7 +23,8 @@ __all__ = [
     "gemm_split3", "gemm_split3_convert", "gemm_split3_workspace_size", "split_one_launch",
     "gemm_backward", "gemm_grouped", "GroupedPlan", "GemmFn", "matmul", "load",
     "GemmError", "GemmArgError", "GEMM_F64", "GEMM_F32", "GEMM_BF16",
-    "tile_configs", "force_tile_config",
+    "tile_configs", "force_tile_config", "gemm_plain_ksplit", "gemm_plain_ksplit_workspace_size",
+    "force_ksplit",
 ]
 
 
@@ -91,6 +92,43 @@ def gemm_plain(A, B, C=None):
     lib = _lib.load()
     _lib.check(lib.gemm_plain(code, m, n, k, pa, lda, pb, ldb, pc, ldc, _stream(A)), "gemm_plain")
     return C
+
+
+def gemm_plain_ksplit_workspace_size(dtype_code, m, n, k) -> int:
+    return int(_lib.load().gemm_plain_ksplit_workspace_size(int(dtype_code), int(m), int(n), int(k)))
+
+
+def gemm_plain_ksplit(A, B, C=None, workspace=None):
+    """C = A @ B like gemm_plain, with the K loop split over workgroups when
+    the product has too few output tiles to occupy the device (partial
+    products in ``workspace``, then added in K order)."""
+    torch = _torch()
+    code = _dtype_code(A)
+    if B.dtype != A.dtype:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain_ksplit", "A and B dtypes differ")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain_ksplit",
+                           f"shape mismatch {tuple(A.shape)} x {tuple(B.shape)}")
+    if C is None:
+        C = torch.empty((m, n), dtype=_out_dtype(code), device=A.device)
+    if workspace is None:
+        need = gemm_plain_ksplit_workspace_size(code, m, n, k)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    lib = _lib.load()
+    _lib.check(lib.gemm_plain_ksplit(code, m, n, k, pa, lda, pb, ldb, pc, ldc,
+                                     ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     _stream(A)), "gemm_plain_ksplit")
+    return C
+
+
+def force_ksplit(parts: int):
+    """Split the K loop of gemm_plain_ksplit into ``parts`` chunks (-1: automatic)."""
+    _lib.check(_lib.load().gemm_plain_ksplit_force(int(parts)), "gemm_plain_ksplit_force")
 
 
 def gemm_split_workspace_size(m, n, k) -> int:

@@ -24,7 +24,8 @@ EXPORTS = (
     "gemm_backward", "gemm_grouped_plan_create", "gemm_grouped_run",
     "gemm_grouped_plan_update", "gemm_grouped_plan_destroy", "gemm_grouped_plan_info",
     "gemm_grouped", "gemm_strerror", "gemm_last_error", "gemm_tile_config_count",
-    "gemm_tile_config_name", "gemm_plain_force_config",
+    "gemm_tile_config_name", "gemm_plain_force_config", "gemm_plain_ksplit_workspace_size",
+    "gemm_plain_ksplit", "gemm_plain_ksplit_force",
 )
 
 
@@ -55,6 +56,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
         sig = {
             "gemm_plain": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]),
             "gemm_split_workspace_size": (sz, [i64, i64, i64]),
+            "gemm_plain_ksplit_workspace_size": (sz, [ci, i64, i64, i64]),
+            "gemm_plain_ksplit": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
+            "gemm_plain_ksplit_force": (ci, [ci]),
             "gemm_split_convert": (ci, [i64, i64, vp, i64, ci, vp, vp, i64, vp]),
             "gemm_split": (ci, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
             "gemm_split3_workspace_size": (sz, [i64, i64, i64]),

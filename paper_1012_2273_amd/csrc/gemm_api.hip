@@ -38,6 +38,7 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 static std::atomic<int> g_force_cfg{-1};
+static std::atomic<int> g_force_parts{-1};
 
 // The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
@@ -284,6 +285,54 @@ static int run_product(int prec, int layout, const GemmArgs &a, size_t es_in, hi
   return GEMM_OK;
 }
 
+static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Widest vector loads both operands of an NN product allow.
+static int nn_vector_width(const GemmArgs &a, size_t es) {
+  if (vec_ok(a.A, a.lda, es, a.K) && vec_ok(a.B, a.ldb, es, a.N)) return 16;
+  if (es < 8 && vec_ok(a.A, a.lda, es, a.K, 8) && vec_ok(a.B, a.ldb, es, a.N, 8)) return 8;
+  return 0;
+}
+
+// K split over workgroups for products with too few output tiles to occupy
+// the device: the tile shape, the number of K chunks and their length kc (a
+// multiple of 64, so every chunk but the last holds whole K-tiles of every
+// precision and starts 16-byte aligned). 64 x 64 tiles, chunks for about
+// three workgroups per CU, each at least 128 deep; binary64 splits while its
+// 64 x 64 tiles number at most two per CU, binary32 and bf16 (whose plain
+// mid-size shapes already split K inside the workgroup) at most one per two
+// CUs. Measured on MI355X, binary64: N = 800 26.2 -> 31.3 TFLOP/s, N = 1200
+// 34.8 -> 45.0, 256 x 256 x 65536 5.5 -> 21.9 at 8 chunks; binary32
+// 256 x 256 x 65536 10.3 -> 35.0; binary32 N = 1000 loses (67.2 -> 60.7).
+// Depends only on the precision, the sizes, the device and the forced
+// settings, so the workspace query and the product agree.
+struct KsplitPlan { int cfg, parts; int64_t kc; };
+static KsplitPlan ksplit_plan(int prec, int64_t m, int64_t n, int64_t k) {
+  KsplitPlan p{CFG_64x64, 1, k};
+  const int fc = g_force_cfg.load();
+  if (fc >= 0 && fc < CFG_COUNT && ksplit_offered(prec, LAYOUT_NN, fc, 16)) p.cfg = fc;
+  const int bm = kCfgs[p.cfg].bm, bn = kCfgs[p.cfg].bn;
+  const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
+  const int64_t cus = device_cus();
+  int64_t parts = 1;
+  const int fp = g_force_parts.load();
+  if (fp > 0) {
+    parts = fp;
+  } else if (tiles > 0 && tiles <= (prec == PREC_F64 ? 2 * cus : cus / 2)) {
+    const int64_t by_slots = 3 * cus / tiles, by_k = k / 128;
+    parts = by_slots < by_k ? by_slots : by_k;
+    if (parts > 1024) parts = 1024;
+  }
+  if (k <= 0 || parts <= 1) return p;
+  p.kc = round_up((k + parts - 1) / parts, 64);
+  p.parts = (int)((k + p.kc - 1) / p.kc);
+  return p;
+}
+
+static size_t ksplit_bytes(int prec, const KsplitPlan &p, int64_t m, int64_t n) {
+  return p.parts <= 1 ? 0 : (size_t)(p.parts - 1) * m * n * (prec == PREC_F64 ? 8 : 4);
+}
+
 }  // namespace g355
 
 using namespace g355;
@@ -336,7 +385,6 @@ int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_
   return run_product(prec, LAYOUT_NN, a, esize_of(dtype), (hipStream_t)stream);
 }
 
-static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Workspace layout: the np planes of A (m rows each), then the np planes of
 // B transposed (n rows each), hi first; each plane starts on a 256-byte
@@ -346,6 +394,59 @@ static int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 // line, so a 16-byte-per-lane transfer of a K-tile touches whole lines
 // (a 4000-byte pitch at k = 2000 made most K-chunks straddle two lines and
 // cost the product 17% at N = 2000).
+static int plain_prec(int dtype) {
+  return dtype == GEMM_F64 ? PREC_F64 : dtype == GEMM_F32 ? PREC_F32 : PREC_BF16;
+}
+
+int gemm_plain_ksplit_force(int parts) {
+  if (parts < -1 || parts == 0 || parts > 65535)
+    return set_error(GEMM_EINVAL, "K chunk count out of range");
+  g_force_parts.store(parts);
+  return GEMM_OK;
+}
+
+size_t gemm_plain_ksplit_workspace_size(int dtype, int64_t m, int64_t n, int64_t k) {
+  if (dtype != GEMM_F64 && dtype != GEMM_F32 && dtype != GEMM_BF16) return 0;
+  if (m <= 0 || n <= 0 || k <= 0) return 0;
+  const int prec = plain_prec(dtype);
+  return ksplit_bytes(prec, ksplit_plan(prec, m, n, k), m, n);
+}
+
+int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, void *C, int64_t ldc, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+  clear_error();
+  if (dtype != GEMM_F64 && dtype != GEMM_F32 && dtype != GEMM_BF16)
+    return set_error(GEMM_EUNSUPPORTED, "dtype " + std::to_string(dtype));
+  if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
+  int rc;
+  if ((rc = check_mat("A", A, m, k, lda)) || (rc = check_mat("B", B, k, n, ldb)) ||
+      (rc = check_mat("C", C, m, n, ldc)))
+    return rc;
+  if (m == 0 || n == 0) return GEMM_OK;
+  const int prec = plain_prec(dtype);
+  const size_t es = esize_of(dtype);
+  GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
+  hipStream_t s = (hipStream_t)stream;
+  const KsplitPlan p = ksplit_plan(prec, m, n, k);
+  if (p.parts <= 1) return run_product(prec, LAYOUT_NN, a, es, s);
+  const size_t need = ksplit_bytes(prec, p, m, n);
+  if (workspace == nullptr || workspace_bytes < need)
+    return set_error(GEMM_EWORKSPACE, "need " + std::to_string(need) + " bytes, got " +
+                                          std::to_string(workspace_bytes));
+  if ((uintptr_t)workspace % 16 != 0)
+    return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
+  if ((rc = check_ld_range("A", lda, es)) || (rc = check_ld_range("B", ldb, es))) return rc;
+  const int vw = nn_vector_width(a, es);
+  if (!ksplit_offered(prec, LAYOUT_NN, p.cfg, vw))
+    return set_error(GEMM_EINVAL, "tile config not offered for the K split");
+  hipError_t e = launch_ksplit(prec, LAYOUT_NN, p.cfg, vw, a, p.parts, p.kc, workspace, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  e = launch_ksplit_sum(prec, C, ldc, workspace, m, n, p.parts - 1, s);
+  if (e != hipSuccess) return hip_fail(e, "sum launch");
+  return GEMM_OK;
+}
+
 static void split_layout(int np, int64_t m, int64_t n, int64_t k, int64_t &kp, int64_t &ldp,
                          size_t off[6], size_t &total) {
   kp = round_up(k > 0 ? k : 1, 8);

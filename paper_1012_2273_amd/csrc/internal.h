@@ -43,6 +43,14 @@ hipError_t launch_plain(int prec, int layout, int cfg, int vw, const GemmArgs &a
 int plain_occupancy(int prec, int layout, int cfg, int vw);
 // Whether a kernel exists for that combination.
 bool plain_offered(int prec, int layout, int cfg, int vw);
+// K split over workgroups (binary64, binary32, bf16): `parts` chunks of kc
+// K-indices, chunk 0 into C, chunk y > 0 into plane y - 1 of ws (M x N
+// outputs each, row pitch N); then C += the planes in chunk order.
+bool ksplit_offered(int prec, int layout, int cfg, int vw);
+hipError_t launch_ksplit(int prec, int layout, int cfg, int vw, const GemmArgs &a, int parts,
+                         int64_t kc, void *ws, hipStream_t stream);
+hipError_t launch_ksplit_sum(int prec, void *C, int64_t ldc, const void *W, int64_t m, int64_t n,
+                             int parts, hipStream_t stream);
 
 // Split kernels (np = 2: hi, lo; np = 3: hi, mid, lo). X (rows x cols, ldx)
 // -> np 16-bit planes. Plane rows are written up to `out_pad` >= their

@@ -25,6 +25,51 @@ gemm_plain_dma_kernel(GemmArgs g, int tiles_m, int tiles_n, int group_m) {
   gemm_tile_dma<P, S, TA, TB>(g, (int64_t)tm * S::BM, (int64_t)tn * S::BN, smem);
 }
 
+// K split over workgroups: blockIdx.y takes K-indices [y kc, (y + 1) kc) of
+// the product; chunk 0 writes its partial product to C, chunk y > 0 to plane
+// y - 1 of the workspace (M x N, row pitch N). kc is a multiple of every
+// K-tile depth and of 16 bytes, so only the last chunk has a ragged K-tile
+// and every chunk's operand base keeps the alignment of the whole operand.
+template <int P, class S, bool TA, bool TB, int VW>
+__global__ void __launch_bounds__(S::NT)
+gemm_ksplit_kernel(GemmArgs g, int tiles_m, int tiles_n, int group_m, int64_t kc, void *ws) {
+  using E = typename Traits<P>::E;
+  using O = typename Traits<P>::Out;
+  constexpr bool DMA = VW == 16 && dma_ok<P, S, TA, TB>();
+  __shared__ __attribute__((aligned(16))) char smem[DMA ? lds_bytes_dma<P, S, TA, TB>()
+                                                        : lds_bytes<P, S>()];
+  const int64_t y = blockIdx.y, k0 = y * kc;
+  g.A = (const E *)g.A + k0 * (TA ? g.lda : 1);
+  g.B = (const E *)g.B + k0 * (TB ? 1 : g.ldb);
+  g.K = g.K - k0 < kc ? g.K - k0 : kc;
+  if (y > 0) {
+    g.C = (O *)ws + (y - 1) * g.M * g.N;
+    g.ldc = g.N;
+  }
+  int tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, group_m, tm, tn);
+  if constexpr (DMA)
+    gemm_tile_dma<P, S, TA, TB>(g, (int64_t)tm * S::BM, (int64_t)tn * S::BN, smem);
+  else
+    gemm_tile<P, S, TA, TB, VW>(g, (int64_t)tm * S::BM, (int64_t)tn * S::BN, smem);
+}
+
+// C += plane 0 + plane 1 + ... + plane (parts - 1), added in that order
+// (the K chunks' order), one thread per output column, rows strided over
+// blockIdx.y.
+template <class O>
+__global__ void __launch_bounds__(256)
+ksplit_sum_kernel(O *C, int64_t ldc, const O *W, int64_t m, int64_t n, int parts) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int64_t mn = m * n;
+  for (int64_t r = blockIdx.y; r < m; r += gridDim.y) {
+    O acc = C[r * ldc + c];
+    for (int p = 0; p < parts; ++p) acc += W[p * mn + r * n + c];
+    C[r * ldc + c] = acc;
+  }
+}
+
 template <int P, class S, bool TA, bool TB, int VW>
 static hipError_t launch_one(const GemmArgs &a, hipStream_t stream) {
   const int64_t tiles_m = (a.M + S::BM - 1) / S::BM;
@@ -153,6 +198,56 @@ hipError_t launch_plain(int prec, int layout, int cfg, int vw, const GemmArgs &a
   };
   const int r = visit(prec, layout, cfg, vw, f);
   return r < 0 ? hipErrorInvalidValue : (hipError_t)r;
+}
+
+// The K split is instantiated for NN products of the plain precisions on
+// the shapes that hold one or two workgroups per CU.
+template <int P, class S, bool TA, bool TB> constexpr bool ksplit_offered() {
+  return (P == PREC_F64 || P == PREC_F32 || P == PREC_BF16) && !TA && !TB &&
+         (std::is_same_v<S, S128x128> || std::is_same_v<S, S128x128w8> ||
+          std::is_same_v<S, S128x64> || std::is_same_v<S, S64x64>);
+}
+
+bool ksplit_offered(int prec, int layout, int cfg, int vw) {
+  auto f = []<int P, class S, bool TA, bool TB, int VW>(KTag<P, S, TA, TB, VW>) -> int {
+    return ksplit_offered<P, S, TA, TB>() ? 0 : -1;
+  };
+  return visit(prec, layout, cfg, vw, f) >= 0;
+}
+
+hipError_t launch_ksplit(int prec, int layout, int cfg, int vw, const GemmArgs &a, int parts,
+                         int64_t kc, void *ws, hipStream_t stream) {
+  auto f = [&]<int P, class S, bool TA, bool TB, int VW>(KTag<P, S, TA, TB, VW>) -> int {
+    if constexpr (!ksplit_offered<P, S, TA, TB>()) {
+      return -1;
+    } else {
+      const int64_t tiles_m = (a.M + S::BM - 1) / S::BM;
+      const int64_t tiles_n = (a.N + S::BN - 1) / S::BN;
+      const int64_t tiles = tiles_m * tiles_n;
+      if (tiles <= 0 || parts < 1) return (int)hipSuccess;
+      if (tiles > 0x7fffffff || parts > 65535) return (int)hipErrorInvalidValue;
+      hipLaunchKernelGGL((gemm_ksplit_kernel<P, S, TA, TB, VW>), dim3((unsigned)tiles, (unsigned)parts),
+                         dim3(S::NT), 0, stream, a, (int)tiles_m, (int)tiles_n, 4, kc, ws);
+      return (int)hipGetLastError();
+    }
+  };
+  const int r = visit(prec, layout, cfg, vw, f);
+  return r < 0 ? hipErrorInvalidValue : (hipError_t)r;
+}
+
+hipError_t launch_ksplit_sum(int prec, void *C, int64_t ldc, const void *W, int64_t m, int64_t n,
+                             int parts, hipStream_t stream) {
+  if (m <= 0 || n <= 0 || parts <= 0) return hipSuccess;
+  const int64_t gx = (n + 255) / 256, gy = m < 4096 ? m : 4096;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(ksplit_sum_kernel<double>, grid, dim3(256), 0, stream, (double *)C, ldc,
+                       (const double *)W, m, n, parts);
+  else
+    hipLaunchKernelGGL(ksplit_sum_kernel<float>, grid, dim3(256), 0, stream, (float *)C, ldc,
+                       (const float *)W, m, n, parts);
+  return hipGetLastError();
 }
 
 int plain_occupancy(int prec, int layout, int cfg, int vw) {
