@@ -139,6 +139,48 @@ def test_split_validation(lib):
     assert lib.gemm_split_convert(4, 5, v(16), 5, 0, None, v(16), 5, None) == _lib.GEMM_ENULL
 
 
+def test_ksplit_workspace_and_validation(lib):
+    """Workspace query (the device's CU count falls back to 256 without a
+    device) and argument checks of the K-split product."""
+    v = ctypes.c_void_p
+    F64, F32 = _lib.GEMM_F64, _lib.GEMM_F32
+    size = lib.gemm_plain_ksplit_workspace_size
+    # 256 x 256 x 65536: 16 tiles of 64 x 64, 48 chunks asked (three workgroups per CU),
+    # 1366 rounded up to 1408 indices each, so 47 chunks (the last 768 deep): 46 planes
+    assert size(F64, 256, 256, 65536) == 46 * 256 * 256 * 8
+    assert size(F32, 256, 256, 65536) == 46 * 256 * 256 * 4
+    assert size(F64, 4096, 4096, 4096) == 0      # enough tiles: unsplit
+    assert size(F64, 512, 512, 64) == 0          # K too short for two 128-deep chunks
+    assert size(7, 256, 256, 65536) == 0 and size(F64, -1, 8, 8) == 0
+    assert lib.gemm_plain_ksplit_force(0) == _lib.GEMM_EINVAL
+    assert lib.gemm_plain_ksplit_force(-2) == _lib.GEMM_EINVAL
+    assert lib.gemm_plain_ksplit_force(3) == _lib.GEMM_OK
+    try:
+        assert size(F64, 64, 64, 1000) == 2 * 64 * 64 * 8   # 3 chunks of 384
+        assert size(F64, 64, 64, 100) == 1 * 64 * 64 * 8    # 2 chunks of 64
+    finally:
+        assert lib.gemm_plain_ksplit_force(-1) == _lib.GEMM_OK
+    m = n = 256
+    k = 65536
+    ws = size(F64, m, n, k)
+
+    def call(**kw):
+        a = dict(dtype=F64, m=m, n=n, k=k, A=v(256), lda=k, B=v(256), ldb=n, C=v(256), ldc=n,
+                 W=v(256), wb=ws)
+        a.update(kw)
+        return lib.gemm_plain_ksplit(a["dtype"], a["m"], a["n"], a["k"], a["A"], a["lda"], a["B"],
+                                     a["ldb"], a["C"], a["ldc"], a["W"], a["wb"], None)
+
+    assert call(W=None) == _lib.GEMM_EWORKSPACE
+    assert call(wb=ws - 1) == _lib.GEMM_EWORKSPACE
+    assert call(W=v(264)) == _lib.GEMM_EWORKSPACE        # not 16-byte aligned
+    assert call(dtype=9) == _lib.GEMM_EUNSUPPORTED
+    assert call(m=-1) == _lib.GEMM_EINVAL
+    assert call(A=None) == _lib.GEMM_ENULL
+    assert call(lda=k - 1) == _lib.GEMM_ELD
+    assert call(m=0, A=None, C=None) == _lib.GEMM_OK
+
+
 def test_backward_validation(lib):
     v = ctypes.c_void_p
     assert lib.gemm_backward(5, 4, 4, 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, None) == _lib.GEMM_EUNSUPPORTED
