@@ -301,9 +301,13 @@ static int nn_vector_width(const GemmArgs &a, size_t es) {
 // three workgroups per CU, each at least 128 deep; binary64 splits while its
 // 64 x 64 tiles number at most two per CU, binary32 and bf16 (whose plain
 // mid-size shapes already split K inside the workgroup) at most one per two
-// CUs. Measured on MI355X, binary64: N = 800 26.2 -> 31.3 TFLOP/s, N = 1200
-// 34.8 -> 45.0, 256 x 256 x 65536 5.5 -> 21.9 at 8 chunks; binary32
-// 256 x 256 x 65536 10.3 -> 35.0; binary32 N = 1000 loses (67.2 -> 60.7).
+// CUs. binary64 products whose 128 x 128 tiles, one per CU, leave chunks
+// at least 1024 deep take the 8-wave 128 x 128 shape instead (twice the
+// flops per operand byte of 64 x 64). Measured on MI355X (TFLOP/s, binary64):
+// N = 800 26.7 -> 30.7, N = 1200 36.3 -> 43.7, 256 x 256 x 65536 5.5 -> 59.0
+// (64 chunks of 128 x 128; 52.3 with 47 of 64 x 64), 512 x 512 x 16384
+// 21.5 -> 59.8, 1024 x 1024 x 8192 51.0 -> 64.0; binary32 256 x 256 x 65536
+// 10.2 -> 77.0; binary32 N = 1000 would lose (67.2 -> 60.7) and stays unsplit.
 // Depends only on the precision, the sizes, the device and the forced
 // settings, so the workspace query and the product agree.
 struct KsplitPlan { int cfg, parts; int64_t kc; };
@@ -316,7 +320,14 @@ static KsplitPlan ksplit_plan(int prec, int64_t m, int64_t n, int64_t k) {
   const int64_t cus = device_cus();
   int64_t parts = 1;
   const int fp = g_force_parts.load();
-  if (fp > 0) {
+  // binary64 with deep chunks: 128 x 128 tiles of 8 waves, one workgroup per
+  // CU, when chunks of at least 1024 indices fill the device
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  if (fp <= 0 && fc < 0 && prec == PREC_F64 && t128 > 0 && 2 * t128 <= cus &&
+      k / 1024 >= cus / t128) {
+    p.cfg = CFG_128x128_W8;
+    parts = cus / t128;
+  } else if (fp > 0) {
     parts = fp;
   } else if (tiles > 0 && tiles <= (prec == PREC_F64 ? 2 * cus : cus / 2)) {
     const int64_t by_slots = 3 * cus / tiles, by_k = k / 128;

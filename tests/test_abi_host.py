@@ -145,10 +145,15 @@ def test_ksplit_workspace_and_validation(lib):
     v = ctypes.c_void_p
     F64, F32 = _lib.GEMM_F64, _lib.GEMM_F32
     size = lib.gemm_plain_ksplit_workspace_size
-    # 256 x 256 x 65536: 16 tiles of 64 x 64, 48 chunks asked (three workgroups per CU),
-    # 1366 rounded up to 1408 indices each, so 47 chunks (the last 768 deep): 46 planes
-    assert size(F64, 256, 256, 65536) == 46 * 256 * 256 * 8
+    # binary64 256 x 256 x 65536: 4 tiles of 128 x 128 on 256 CUs, 64 chunks of 1024: 63 planes
+    assert size(F64, 256, 256, 65536) == 63 * 256 * 256 * 8
+    # binary32: 16 tiles of 64 x 64, 48 chunks asked (three workgroups per CU), 1366 rounded
+    # up to 1408 indices each, so 47 chunks (the last 768 deep): 46 planes
     assert size(F32, 256, 256, 65536) == 46 * 256 * 256 * 4
+    # binary64 128 x 2048 x 4096: 16 chunks of 128 x 128 would be 256 deep: 64 x 64 rule,
+    # 64 tiles, 12 chunks asked, 342 rounded up to 384 indices each, so 11 chunks (the last
+    # 256 deep): 10 planes
+    assert size(F64, 128, 2048, 4096) == 10 * 128 * 2048 * 8
     assert size(F64, 4096, 4096, 4096) == 0      # enough tiles: unsplit
     assert size(F64, 512, 512, 64) == 0          # K too short for two 128-deep chunks
     assert size(7, 256, 256, 65536) == 0 and size(F64, -1, 8, 8) == 0

@@ -114,7 +114,8 @@ def test_more_chunks_than_k_allows(G):
         G.force_ksplit(-1)
 
 
-@pytest.mark.parametrize("shape", [(1000, 1000, 1000), (256, 256, 65536), (800, 640, 1200)])
+@pytest.mark.parametrize("shape", [(1000, 1000, 1000), (256, 256, 65536), (800, 640, 1200),
+                                   (1024, 1024, 8192)])
 def test_automatic_split_binary64(G, shape):
     """The sizes the split is meant for: it splits them, and matches the
     oracle over the whole product."""
