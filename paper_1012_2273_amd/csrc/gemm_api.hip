@@ -306,8 +306,12 @@ static int nn_vector_width(const GemmArgs &a, size_t es) {
 // flops per operand byte of 64 x 64). Measured on MI355X (TFLOP/s, binary64):
 // N = 800 26.7 -> 30.7, N = 1200 36.3 -> 43.7, 256 x 256 x 65536 5.5 -> 59.0
 // (64 chunks of 128 x 128; 52.3 with 47 of 64 x 64), 512 x 512 x 16384
-// 21.5 -> 59.8, 1024 x 1024 x 8192 51.0 -> 64.0; binary32 256 x 256 x 65536
-// 10.2 -> 77.0; binary32 N = 1000 would lose (67.2 -> 60.7) and stays unsplit.
+// 21.5 -> 59.8, 1024 x 1024 x 8192 51.0 -> 64.0; binary32 N = 1000 would
+// lose (67.2 -> 60.7) and stays unsplit. binary32 and bf16 products whose
+// 128 x 128 tiles, two per CU, leave chunks at least 512 deep take that
+// shape (1024 x 1024 x 8192: binary32 91.3 -> 117.0 against the 64 x 64
+// rule, bf16 188.5 -> 455.7; 256 x 256 x 65536: binary32 10.2 unsplit, 79.7
+// with 64 x 64, 92.1).
 // Depends only on the precision, the sizes, the device and the forced
 // settings, so the workspace query and the product agree.
 struct KsplitPlan { int cfg, parts; int64_t kc; };
@@ -323,10 +327,16 @@ static KsplitPlan ksplit_plan(int prec, int64_t m, int64_t n, int64_t k) {
   // binary64 with deep chunks: 128 x 128 tiles of 8 waves, one workgroup per
   // CU, when chunks of at least 1024 indices fill the device
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  // binary32/bf16 likewise with 4-wave 128 x 128 tiles, two per CU, when
+  // chunks of at least 512 indices fill the device
   if (fp <= 0 && fc < 0 && prec == PREC_F64 && t128 > 0 && 2 * t128 <= cus &&
       k / 1024 >= cus / t128) {
     p.cfg = CFG_128x128_W8;
     parts = cus / t128;
+  } else if (fp <= 0 && fc < 0 && prec != PREC_F64 && t128 > 0 && t128 <= cus &&
+             k / 512 >= 2 * cus / t128) {
+    p.cfg = CFG_128x128;
+    parts = 2 * cus / t128;
   } else if (fp > 0) {
     parts = fp;
   } else if (tiles > 0 && tiles <= (prec == PREC_F64 ? 2 * cus : cus / 2)) {

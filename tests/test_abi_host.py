@@ -147,9 +147,11 @@ def test_ksplit_workspace_and_validation(lib):
     size = lib.gemm_plain_ksplit_workspace_size
     # binary64 256 x 256 x 65536: 4 tiles of 128 x 128 on 256 CUs, 64 chunks of 1024: 63 planes
     assert size(F64, 256, 256, 65536) == 63 * 256 * 256 * 8
-    # binary32: 16 tiles of 64 x 64, 48 chunks asked (three workgroups per CU), 1366 rounded
-    # up to 1408 indices each, so 47 chunks (the last 768 deep): 46 planes
-    assert size(F32, 256, 256, 65536) == 46 * 256 * 256 * 4
+    # binary32: 4 tiles of 128 x 128, two per CU: 128 chunks of 512: 127 planes
+    assert size(F32, 256, 256, 65536) == 127 * 256 * 256 * 4
+    # binary32 1000 x 1000 x 1000: 64 tiles of 128 x 128 would give 8 chunks of 125; 256
+    # tiles of 64 x 64, more than one per two CUs: unsplit
+    assert size(F32, 1000, 1000, 1000) == 0
     # binary64 128 x 2048 x 4096: 16 chunks of 128 x 128 would be 256 deep: 64 x 64 rule,
     # 64 tiles, 12 chunks asked, 342 rounded up to 384 indices each, so 11 chunks (the last
     # 256 deep): 10 planes

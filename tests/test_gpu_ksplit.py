@@ -128,8 +128,9 @@ def test_automatic_split_binary64(G, shape):
     assert err <= 1e-12
 
 
-def test_automatic_split_binary32_deep_k(G):
-    m, n, k = 256, 192, 20000
+@pytest.mark.parametrize("shape", [(256, 192, 20000), (1024, 1024, 4096)])
+def test_automatic_split_binary32_deep_k(G, shape):
+    m, n, k = shape
     assert G.gemm_plain_ksplit_workspace_size(G.GEMM_F32, m, n, k) > 0
     A, B = inputs.uniform_mnk(m, n, k, 31, dtype=np.float32)
     got = _run(G, A, B, "f32")
