@@ -78,7 +78,7 @@ int gemm_plain(int dtype, int64_t m, int64_t n, int64_t k,
  * gemm_plain_ksplit_workspace_size -- bytes of device workspace
  * gemm_plain_ksplit needs for this product: (chunks - 1) * m * n output
  * elements (C's type), 0 when the product runs unsplit. Depends on the
- * sizes, the device's CU count and the forced settings below only.
+ * sizes, the device's CU count and this thread's forced settings only.
  * Returns 0 for an unknown dtype or a size <= 0.
  */
 size_t gemm_plain_ksplit_workspace_size(int dtype, int64_t m, int64_t n, int64_t k);
@@ -93,7 +93,9 @@ size_t gemm_plain_ksplit_workspace_size(int dtype, int64_t m, int64_t n, int64_t
  * planes to C in chunk order. The association of the sum over K differs
  * from gemm_plain's (one partial sum per chunk), the result is the same for
  * every call with the same sizes on the same device. Products with enough
- * tiles run as gemm_plain and leave the workspace untouched.
+ * tiles run as gemm_plain and leave the workspace untouched. (The chunk
+ * count and shape can be forced per thread for tests and tuning, see
+ * gemm_mi355x_tuning.h.)
  *   workspace, workspace_bytes  device memory owned by the caller, 16-byte
  *     aligned, at least gemm_plain_ksplit_workspace_size(dtype, m, n, k)
  *     bytes (NULL with 0 allowed when that is 0); its contents on entry do
@@ -106,15 +108,6 @@ int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k,
                       const void *A, int64_t lda, const void *B, int64_t ldb,
                       void *C, int64_t ldc, void *workspace, size_t workspace_bytes,
                       void *stream);
-
-/*
- * gemm_plain_ksplit_force -- make gemm_plain_ksplit cut K into `parts`
- * chunks of a multiple of 64 indices each (fewer if K is short; -1 restores
- * the automatic count). The tile shape follows gemm_plain_force_config when
- * that names 128x128, 128x128w8, 128x64 or 64x64. For tests and tuning.
- * Errors: EINVAL (parts 0, below -1 or above 65535).
- */
-int gemm_plain_ksplit_force(int parts);
 
 /*
  * gemm_split_workspace_size -- bytes of device workspace gemm_split needs
@@ -150,6 +143,12 @@ int gemm_split_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
  *              bytes, owned by the caller, 16-byte aligned; it holds the
  *              planes between the split launch and the product launch, so it
  *              must not be shared by overlapping calls.
+ * Workspace layout after a two-step call (16-bit patterns; kp = k rounded up
+ * to 8, row pitch ldp = kp rounded up to 64 elements; each plane starts on a
+ * 256-byte boundary, in this order): A_hi, A_lo, each m rows of ldp holding
+ * A's rows (element (r, c) at r*ldp + c); then B_hi, B_lo, each n rows of ldp
+ * holding B's columns (B transposed: element (r, c) of B at c*ldp + r).
+ * Columns [k, kp) of every plane row hold zeros, [kp, ldp) are not written.
  * Small products (see gemm_split_one_launch) run as one launch that splits
  * each operand fragment in registers instead; the result is the same bit
  * for bit and the workspace is then left untouched (it is still required).
@@ -206,7 +205,8 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
  *   workspace  device memory of at least gemm_split3_workspace_size(m, n, k)
  *              bytes, owned by the caller, 16-byte aligned, not shared by
  *              overlapping calls. Small products run as one launch, as for
- *              gemm_split.
+ *              gemm_split. After a two-step call it holds A_hi, A_mid, A_lo,
+ *              B_hi, B_mid, B_lo in the layout gemm_split describes.
  * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
  */
 int gemm_split3(int64_t m, int64_t n, int64_t k,
@@ -275,8 +275,13 @@ int gemm_grouped_run(gemm_plan *plan, void *stream);
 
 /* gemm_grouped_plan_update -- replace the A, B, C pointers (and nothing else)
  * of every problem; sizes and leading dimensions must equal the plan's.
- * Takes effect for the next run without re-capture; synchronous copy.
- * Errors: ENULL, EINVAL (count or a size differs), EHIP. */
+ * A problem whose A and B were 16-byte aligned at plan creation runs in the
+ * kernel that moves operands in 16-byte transfers: its new A and B must be
+ * 16-byte aligned as well (other problems take any alignment). Takes effect
+ * for the next run without re-capture; synchronous copy. Nothing changes
+ * when the call fails.
+ * Errors: ENULL, EINVAL (count or a size differs, or a 16-byte planned
+ * problem gets operands that are not 16-byte aligned), EHIP. */
 int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t count);
 
 /* gemm_grouped_plan_destroy -- free the plan (NULL is a no-op). */
@@ -303,12 +308,12 @@ const char *gemm_strerror(int status);
 const char *gemm_last_error(void);
 
 /* gemm_tile_config_count / gemm_tile_config_name -- the tile shapes the
- * kernels are built for, as "BMxBNxBK"; gemm_plain_force_config(id) makes
- * gemm_plain use tile config `id` for every dtype (-1 restores the
- * size-based choice); used by the autotuner and by the tests. */
+ * kernels are built for, named "BMxBN" plus a suffix: w8 (8 waves), k2 / k4
+ * (two or four waves per output position, each taking a part of every
+ * K-tile); "" for an id out of range. The grouped plan info reports its
+ * policy with these ids. */
 int gemm_tile_config_count(void);
 const char *gemm_tile_config_name(int id);
-int gemm_plain_force_config(int id);
 
 #ifdef __cplusplus
 }

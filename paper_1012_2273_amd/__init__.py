@@ -73,6 +73,34 @@ def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
+def _check_out(C, shape, dtype, like, where, name="C"):
+    """A caller-supplied output must have the product's shape, the output
+    dtype of the call and live on the inputs' device: the kernels write
+    shape[0] x shape[1] elements of that dtype through its pointer."""
+    if tuple(C.shape) != tuple(shape):
+        raise GemmArgError(_lib.GEMM_EINVAL, where,
+                           f"{name} has shape {tuple(C.shape)}, expected {tuple(shape)}")
+    if C.dtype != dtype:
+        raise GemmArgError(_lib.GEMM_EINVAL, where, f"{name} has dtype {C.dtype}, expected {dtype}")
+    if C.device != like.device:
+        raise GemmArgError(_lib.GEMM_EINVAL, where,
+                           f"{name} is on {C.device}, the inputs on {like.device}")
+
+
+def _workspace(ws, need, like, where):
+    """(pointer, size in bytes) of a caller workspace, allocated when absent.
+    It must be a contiguous device tensor on the inputs' device."""
+    torch = _torch()
+    if ws is None:
+        ws = torch.empty(max(int(need), 1), dtype=torch.uint8, device=like.device)
+    if not ws.is_cuda or ws.device != like.device:
+        raise GemmArgError(_lib.GEMM_EINVAL, where,
+                           f"workspace must be a device tensor on {like.device}")
+    if not ws.is_contiguous():
+        raise GemmArgError(_lib.GEMM_EINVAL, where, "workspace must be contiguous")
+    return ws, ctypes.c_void_p(ws.data_ptr()), int(ws.numel() * ws.element_size())
+
+
 def gemm_plain(A, B, C=None):
     """C = A @ B on the matrix cores. float64, float32, or bfloat16 inputs
     (bfloat16 gives a float32 C). Writes into ``C`` if given."""
@@ -86,6 +114,8 @@ def gemm_plain(A, B, C=None):
         raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain", f"shape mismatch {tuple(A.shape)} x {tuple(B.shape)}")
     if C is None:
         C = torch.empty((m, n), dtype=_out_dtype(code), device=A.device)
+    else:
+        _check_out(C, (m, n), _out_dtype(code), A, "gemm_plain")
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
@@ -113,22 +143,24 @@ def gemm_plain_ksplit(A, B, C=None, workspace=None):
                            f"shape mismatch {tuple(A.shape)} x {tuple(B.shape)}")
     if C is None:
         C = torch.empty((m, n), dtype=_out_dtype(code), device=A.device)
-    if workspace is None:
-        need = gemm_plain_ksplit_workspace_size(code, m, n, k)
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    else:
+        _check_out(C, (m, n), _out_dtype(code), A, "gemm_plain_ksplit")
+    need = gemm_plain_ksplit_workspace_size(code, m, n, k) if workspace is None else 0
+    workspace, pw, wbytes = _workspace(workspace, need, A, "gemm_plain_ksplit")
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
     lib = _lib.load()
-    _lib.check(lib.gemm_plain_ksplit(code, m, n, k, pa, lda, pb, ldb, pc, ldc,
-                                     ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+    _lib.check(lib.gemm_plain_ksplit(code, m, n, k, pa, lda, pb, ldb, pc, ldc, pw, wbytes,
                                      _stream(A)), "gemm_plain_ksplit")
     return C
 
 
 def force_ksplit(parts: int):
-    """Split the K loop of gemm_plain_ksplit into ``parts`` chunks (-1: automatic)."""
-    _lib.check(_lib.load().gemm_plain_ksplit_force(int(parts)), "gemm_plain_ksplit_force")
+    """Split the K loop of this thread's gemm_plain_ksplit calls into
+    ``parts`` chunks (-1: automatic). A tuning knob for tests and tools."""
+    _lib.check(_lib.load().gemm_tuning_force_ksplit_parts(int(parts)),
+               "gemm_tuning_force_ksplit_parts")
 
 
 def gemm_split_workspace_size(m, n, k) -> int:
@@ -149,15 +181,15 @@ def _split_product(name, size_fn, A, B, C, workspace):
         raise GemmArgError(_lib.GEMM_EINVAL, name, "shape mismatch")
     if C is None:
         C = torch.empty((m, n), dtype=torch.float32, device=A.device)
-    need = size_fn(m, n, k)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    else:
+        _check_out(C, (m, n), torch.float32, A, name)
+    need = size_fn(m, n, k) if workspace is None else 0
+    workspace, pw, wbytes = _workspace(workspace, need, A, name)
     pa, lda = _mat(A, "A")
     pb, ldb = _mat(B, "B")
     pc, ldc = _mat(C, "C")
     lib = _lib.load()
-    _lib.check(getattr(lib, name)(m, n, k, pa, lda, pb, ldb, pc, ldc,
-                                  ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+    _lib.check(getattr(lib, name)(m, n, k, pa, lda, pb, ldb, pc, ldc, pw, wbytes,
                                   _stream(A)), name)
     return C
 
@@ -240,6 +272,18 @@ def gemm_backward(A, B, dC, need_dA=True, need_dB=True):
     return dA, dB
 
 
+def _check_group(As, Bs, Cs, where):
+    """Every problem's operands agree in dtype and inner size, and every C has
+    the problem's output shape, the operands' dtype and device."""
+    if not (len(As) == len(Bs) == len(Cs)):
+        raise GemmArgError(_lib.GEMM_EINVAL, where, "list lengths differ")
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0] or \
+                A.dtype != As[0].dtype or B.dtype != As[0].dtype:
+            raise GemmArgError(_lib.GEMM_EINVAL, where, f"shape or dtype mismatch (problem {i})")
+        _check_out(C, (A.shape[0], B.shape[1]), A.dtype, A, where, name=f"C[{i}]")
+
+
 def _problems(As, Bs, Cs):
     arr = (_lib.GemmProblem * len(As))()
     for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
@@ -266,9 +310,7 @@ class GroupedPlan:
         if Cs is None:
             Cs = [torch.empty((A.shape[0], B.shape[1]), dtype=A.dtype, device=A.device)
                   for A, B in zip(As, Bs)]
-        for A, B in zip(As, Bs):
-            if A.shape[1] != B.shape[0] or A.dtype != As[0].dtype or B.dtype != As[0].dtype:
-                raise GemmArgError(_lib.GEMM_EINVAL, "GroupedPlan", "shape or dtype mismatch")
+        _check_group(As, Bs, Cs, "GroupedPlan")
         self.As, self.Bs, self.Cs = list(As), list(Bs), list(Cs)
         self._arr = _problems(self.As, self.Bs, self.Cs)
         self.device = As[0].device if As else torch.device("cuda:0")
@@ -292,6 +334,7 @@ class GroupedPlan:
     def update(self, As, Bs, Cs):
         """Point the plan at new tensors of identical shapes (no re-capture)."""
         torch = _torch()
+        _check_group(As, Bs, Cs, "GroupedPlan.update")
         torch.cuda.current_stream(self.device).synchronize()
         arr = _problems(As, Bs, Cs)
         _lib.check(_lib.load().gemm_grouped_plan_update(self._h, arr, len(As)),
@@ -326,6 +369,7 @@ def gemm_grouped(As, Bs, Cs=None):
     if not As:
         return Cs
     code = _dtype_code(As[0])
+    _check_group(As, Bs, Cs, "gemm_grouped")
     arr = _problems(As, Bs, Cs)
     _lib.check(_lib.load().gemm_grouped(code, arr, len(As), _stream(As[0])), "gemm_grouped")
     return Cs
@@ -337,8 +381,10 @@ def tile_configs():
 
 
 def force_tile_config(cfg_id: int):
-    """Use tile config ``cfg_id`` for every single-product launch (-1: automatic)."""
-    _lib.check(_lib.load().gemm_plain_force_config(int(cfg_id)), "gemm_plain_force_config")
+    """Use tile config ``cfg_id`` for this thread's single-product launches
+    (-1: automatic). A tuning knob for tests and tools."""
+    _lib.check(_lib.load().gemm_tuning_force_tile_config(int(cfg_id)),
+               "gemm_tuning_force_tile_config")
 
 
 def _gemm_fn():

@@ -24,9 +24,10 @@ EXPORTS = (
     "gemm_backward", "gemm_grouped_plan_create", "gemm_grouped_run",
     "gemm_grouped_plan_update", "gemm_grouped_plan_destroy", "gemm_grouped_plan_info",
     "gemm_grouped", "gemm_strerror", "gemm_last_error", "gemm_tile_config_count",
-    "gemm_tile_config_name", "gemm_plain_force_config", "gemm_plain_ksplit_workspace_size",
-    "gemm_plain_ksplit", "gemm_plain_ksplit_force",
+    "gemm_tile_config_name", "gemm_plain_ksplit_workspace_size", "gemm_plain_ksplit",
 )
+# the tuning knobs of include/gemm_mi355x_tuning.h (tests and tuning tools)
+TUNING_EXPORTS = ("gemm_tuning_force_tile_config", "gemm_tuning_force_ksplit_parts")
 
 
 class GemmProblem(ctypes.Structure):
@@ -58,7 +59,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
             "gemm_split_workspace_size": (sz, [i64, i64, i64]),
             "gemm_plain_ksplit_workspace_size": (sz, [ci, i64, i64, i64]),
             "gemm_plain_ksplit": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
-            "gemm_plain_ksplit_force": (ci, [ci]),
+            "gemm_tuning_force_ksplit_parts": (ci, [ci]),
             "gemm_split_convert": (ci, [i64, i64, vp, i64, ci, vp, vp, i64, vp]),
             "gemm_split": (ci, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
             "gemm_split3_workspace_size": (sz, [i64, i64, i64]),
@@ -78,7 +79,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
             "gemm_last_error": (ctypes.c_char_p, []),
             "gemm_tile_config_count": (ci, []),
             "gemm_tile_config_name": (ctypes.c_char_p, [ci]),
-            "gemm_plain_force_config": (ci, [ci]),
+            "gemm_tuning_force_tile_config": (ci, [ci]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "gemm_mi355x.h"
+#include "gemm_mi355x_tuning.h"
 #include "gemm_tile.hpp"
 #include "internal.h"
 
@@ -37,8 +38,10 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
                                          {64, 64, "64x64k4"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
-static std::atomic<int> g_force_cfg{-1};
-static std::atomic<int> g_force_parts{-1};
+// Tuning knobs (gemm_mi355x_tuning.h): per calling thread, so a test or a
+// tuning tool that forces a shape never changes another thread's launches.
+static thread_local int t_force_cfg = -1;
+static thread_local int t_force_parts = -1;
 
 // The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
@@ -186,7 +189,7 @@ static double round_cost(int prec, int layout, int vw, int cfg, int64_t m, int64
 // binary64/binary32 step down to the 64 x 64 shape when the round count
 // says it is at least 15% faster.
 static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
-  const int forced = g_force_cfg.load();
+  const int forced = t_force_cfg;
   if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced) &&
       plain_offered(prec, layout, forced, vw))
     return forced;
@@ -317,13 +320,13 @@ static int nn_vector_width(const GemmArgs &a, size_t es) {
 struct KsplitPlan { int cfg, parts; int64_t kc; };
 static KsplitPlan ksplit_plan(int prec, int64_t m, int64_t n, int64_t k) {
   KsplitPlan p{CFG_64x64, 1, k};
-  const int fc = g_force_cfg.load();
+  const int fc = t_force_cfg;
   if (fc >= 0 && fc < CFG_COUNT && ksplit_offered(prec, LAYOUT_NN, fc, 16)) p.cfg = fc;
   const int bm = kCfgs[p.cfg].bm, bn = kCfgs[p.cfg].bn;
   const int64_t tiles = ((m + bm - 1) / bm) * ((n + bn - 1) / bn);
   const int64_t cus = device_cus();
   int64_t parts = 1;
-  const int fp = g_force_parts.load();
+  const int fp = t_force_parts;
   // binary64 with deep chunks: 128 x 128 tiles of 8 waves, one workgroup per
   // CU, when chunks of at least 1024 indices fill the device
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
@@ -384,9 +387,10 @@ const char *gemm_tile_config_name(int id) {
   return kCfgs[id].name;
 }
 
-int gemm_plain_force_config(int id) {
+int gemm_tuning_force_tile_config(int id) {
+  clear_error();
   if (id >= CFG_COUNT || id < -1) return set_error(GEMM_EINVAL, "tile config id out of range");
-  g_force_cfg.store(id);
+  t_force_cfg = id;
   return GEMM_OK;
 }
 
@@ -419,10 +423,11 @@ static int plain_prec(int dtype) {
   return dtype == GEMM_F64 ? PREC_F64 : dtype == GEMM_F32 ? PREC_F32 : PREC_BF16;
 }
 
-int gemm_plain_ksplit_force(int parts) {
+int gemm_tuning_force_ksplit_parts(int parts) {
+  clear_error();
   if (parts < -1 || parts == 0 || parts > 65535)
     return set_error(GEMM_EINVAL, "K chunk count out of range");
-  g_force_parts.store(parts);
+  t_force_parts = parts;
   return GEMM_OK;
 }
 

@@ -69,9 +69,15 @@ template <> struct Traits<PREC_BF16> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
   static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4, CVT = 0;
 };
+#ifndef G355_SPLIT_BK
+#define G355_SPLIT_BK 64
+#endif
+#ifndef G355_BF16_W8_BK
+#define G355_BF16_W8_BK 32
+#endif
 template <> struct Traits<PREC_SPLIT> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 64, PLANES = 2, GRP = 4, CVT = 0;   // hi and lo planes
+  static constexpr int KPL = 8, BK = G355_SPLIT_BK, PLANES = 2, GRP = 4, CVT = 0;   // hi and lo planes
 };
 template <> struct Traits<PREC_SPLIT3> {
   using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
@@ -83,7 +89,7 @@ template <> struct Traits<PREC_SPLIT3> {
 // bit for bit.
 template <> struct Traits<PREC_FSPLIT> {
   using E = float; using Op = u16x8; using Acc = f32x4; using Out = float;
-  static constexpr int KPL = 8, BK = 64, PLANES = 1, GRP = 4, CVT = 2;
+  static constexpr int KPL = 8, BK = G355_SPLIT_BK, PLANES = 1, GRP = 4, CVT = 2;
 };
 template <> struct Traits<PREC_FSPLIT3> {
   using E = float; using Op = u16x8; using Acc = f32x4; using Out = float;
@@ -187,6 +193,8 @@ template <int P, class S> __host__ __device__ constexpr int bk_of() {
     constexpr bool even16 = (S::BM * 16 * 4 / 1024) % waves == 0 && (S::BN * 16 * 4 / 1024) % waves == 0;
     constexpr bool big4 = S::NT == 256 && S::BM * S::BN >= 128 * 128;
     return even16 && !big4 ? 16 : 32;
+  } else if constexpr (P == PREC_BF16 && S::NT >= 512 && S::BM * S::BN == 128 * 128) {
+    return G355_BF16_W8_BK;
   } else {
     return Traits<P>::BK;
   }

@@ -259,6 +259,9 @@ template <int P, class S> struct Geom {
 #define G355_RING16_KB 48
 #endif
 constexpr int kRing16 = G355_RING16_KB * 1024;
+#ifndef G355_RING16_W8_KB
+#define G355_RING16_W8_KB 48
+#endif
 
 // Wait until at most n K-tiles of DPW transfers each are still in flight
 // (0 <= n <= MAXT; n is the same on every lane).
@@ -307,7 +310,8 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   // workgroup), and 144 KiB of the 160 KiB LDS for 8-wave shapes. 16-bit: as
   // many stages as fit in the 16-bit ring budget (2 to 8). vmcnt (6 bits)
   // bounds the transfers a wave may leave outstanding.
-  static constexpr int FIT = (T::KPL == 8 ? kRing16 : (S::NT <= 256 ? 72 : 144) * 1024) / STAGE;
+  static constexpr int R16 = (S::NT >= 512 && S::BM * S::BN <= 128 * 128) ? G355_RING16_W8_KB * 1024 : kRing16;
+  static constexpr int FIT = (T::KPL == 8 ? R16 : (S::NT <= 256 ? 72 : 144) * 1024) / STAGE;
   static constexpr int VMAX = 1 + 63 / (PER_WAVE > 0 ? PER_WAVE : 1);
   static constexpr int NS0 = T::KPL == 8 ? (FIT < 8 ? FIT : 8) : (FIT >= 3 ? 3 : 2);
   static constexpr int NS1 = NS0 < VMAX ? NS0 : VMAX;

@@ -427,10 +427,19 @@ int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t
       return set_error(GEMM_EINVAL, "shape differs at problem " + std::to_string(i));
     if (q.m > 0 && q.n > 0 && (q.C == nullptr || (q.k > 0 && (!q.A || !q.B))))
       return set_error(GEMM_ENULL, "NULL matrix at problem " + std::to_string(i));
+    // the captured work list runs each problem in the kernel its planned
+    // operands allowed: a problem planned with 16-byte transfers keeps them,
+    // so its new A and B must allow them too
+    if (plan->dprob_host[i].vec && !to_device(q, es).vec)
+      return set_error(GEMM_EINVAL, "problem " + std::to_string(i) +
+                                        " was planned with 16-byte aligned operands; the new A or "
+                                        "B is not 16-byte aligned");
   }
   for (int32_t i = 0; i < count; ++i) {
+    const int32_t planned = plan->dprob_host[i].vec;
     plan->probs[i] = probs[i];
     plan->dprob_host[i] = to_device(probs[i], es);
+    plan->dprob_host[i].vec = planned;   // the work list's split stays as captured
   }
   if (count > 0) {
     hipError_t e = hipMemcpy(plan->d_probs, plan->dprob_host.data(),

@@ -11,6 +11,7 @@ from paper_1012_2273_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gemm_mi355x.h")
+TUNING_HEADER = os.path.join(ROOT, "include", "gemm_mi355x_tuning.h")
 
 
 @pytest.fixture(scope="module")
@@ -21,8 +22,8 @@ def lib():
     return _lib.load()
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(gemm_[a-z0-9_]+)\s*\(", text)))
 
@@ -36,8 +37,36 @@ def test_header_declares_the_four_calls():
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
     assert set(names) == set(_lib.EXPORTS)
-    for n in names:
+    tuning = _declared(TUNING_HEADER)
+    assert set(tuning) == set(_lib.TUNING_EXPORTS)
+    for n in names + tuning:
         assert hasattr(lib, n), n
+
+
+def test_every_header_is_covered():
+    """Each header under include/ is one of the two whose symbols are checked."""
+    hs = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert hs == ["gemm_mi355x.h", "gemm_mi355x_tuning.h"]
+
+
+def test_tuning_knobs_are_per_thread(lib):
+    """A forced shape or chunk count on one thread leaves another thread's
+    choice alone (the workspace query reads the calling thread's setting)."""
+    import threading
+    F64 = _lib.GEMM_F64
+    size = lib.gemm_plain_ksplit_workspace_size
+    auto = size(F64, 64, 64, 1000)
+    seen = {}
+    assert lib.gemm_tuning_force_ksplit_parts(3) == _lib.GEMM_OK
+    try:
+        assert size(F64, 64, 64, 1000) == 2 * 64 * 64 * 8
+        t = threading.Thread(target=lambda: seen.update(other=size(F64, 64, 64, 1000)))
+        t.start()
+        t.join()
+    finally:
+        assert lib.gemm_tuning_force_ksplit_parts(-1) == _lib.GEMM_OK
+    assert seen["other"] == auto
+    assert size(F64, 64, 64, 1000) == auto
 
 
 def test_strerror_texts(lib):
@@ -51,8 +80,9 @@ def test_tile_config_names(lib):
     names = [lib.gemm_tile_config_name(i).decode() for i in range(n)]
     assert names[0] == "128x128" and len(set(names)) == n
     assert lib.gemm_tile_config_name(n) == b""
-    assert lib.gemm_plain_force_config(n) == _lib.GEMM_EINVAL
-    assert lib.gemm_plain_force_config(-1) == _lib.GEMM_OK
+    assert lib.gemm_tuning_force_tile_config(n) == _lib.GEMM_EINVAL
+    assert lib.gemm_tuning_force_tile_config(-2) == _lib.GEMM_EINVAL
+    assert lib.gemm_tuning_force_tile_config(-1) == _lib.GEMM_OK
 
 
 def _plain(lib, dtype=0, m=4, n=4, k=4, A=16, lda=4, B=16, ldb=4, C=16, ldc=4):
@@ -159,14 +189,14 @@ def test_ksplit_workspace_and_validation(lib):
     assert size(F64, 4096, 4096, 4096) == 0      # enough tiles: unsplit
     assert size(F64, 512, 512, 64) == 0          # K too short for two 128-deep chunks
     assert size(7, 256, 256, 65536) == 0 and size(F64, -1, 8, 8) == 0
-    assert lib.gemm_plain_ksplit_force(0) == _lib.GEMM_EINVAL
-    assert lib.gemm_plain_ksplit_force(-2) == _lib.GEMM_EINVAL
-    assert lib.gemm_plain_ksplit_force(3) == _lib.GEMM_OK
+    assert lib.gemm_tuning_force_ksplit_parts(0) == _lib.GEMM_EINVAL
+    assert lib.gemm_tuning_force_ksplit_parts(-2) == _lib.GEMM_EINVAL
+    assert lib.gemm_tuning_force_ksplit_parts(3) == _lib.GEMM_OK
     try:
         assert size(F64, 64, 64, 1000) == 2 * 64 * 64 * 8   # 3 chunks of 384
         assert size(F64, 64, 64, 100) == 1 * 64 * 64 * 8    # 2 chunks of 64
     finally:
-        assert lib.gemm_plain_ksplit_force(-1) == _lib.GEMM_OK
+        assert lib.gemm_tuning_force_ksplit_parts(-1) == _lib.GEMM_OK
     m = n = 256
     k = 65536
     ws = size(F64, m, n, k)

@@ -124,6 +124,42 @@ def test_plan_update_new_pointers(G):
     plan.close()
 
 
+def test_plan_update_rejects_misaligned_views(G):
+    """A problem planned with 16-byte aligned operands runs in the kernel of
+    16-byte transfers: an update to an offset view (8-byte aligned binary64)
+    is refused, the plan keeps its old pointers and still computes them."""
+    torch = _torch()
+    n = 64                                   # even: 16-byte rows, planned aligned
+    A, B = inputs.uniform_square(n, 505)
+    Ad, Bd = dev(A, torch), dev(B, torch)
+    plan = G.GroupedPlan([Ad], [Bd])
+    C0 = plan.Cs[0]
+    big = torch.zeros((n, n + 1), dtype=torch.float64, device="cuda:0")
+    big[:, 1:] = Ad
+    view = big[:, 1:]                        # base 8 bytes past a 16-byte boundary
+    assert view.data_ptr() % 16 == 8
+    with pytest.raises(ValueError, match="16-byte"):
+        plan.update([view], [Bd], [torch.empty_like(C0)])
+    C0.zero_()
+    plan.run()
+    torch.cuda.synchronize()
+    assert oracle.relerr_fro(C0.cpu().numpy(), oracle.gemm(A, B)) <= 1e-12
+    # an odd-sized problem is planned for any alignment and takes the view
+    m = 63
+    A3, B3 = inputs.uniform_square(m, 506)
+    A3d, B3d = dev(A3, torch), dev(B3, torch)
+    plan3 = G.GroupedPlan([A3d], [B3d])
+    big3 = torch.zeros((m, m + 1), dtype=torch.float64, device="cuda:0")
+    big3[:, 1:] = A3d
+    C3 = torch.empty((m, m), dtype=torch.float64, device="cuda:0")
+    plan3.update([big3[:, 1:]], [B3d], [C3])
+    plan3.run()
+    torch.cuda.synchronize()
+    assert oracle.relerr_fro(C3.cpu().numpy(), oracle.gemm(A3, B3)) <= 1e-12
+    plan.close()
+    plan3.close()
+
+
 def test_uncaptured_and_edge_problems(G):
     torch = _torch()
     shapes = [(5, 7, 3), (0, 4, 4), (6, 0, 2), (9, 9, 0), (1, 1, 1), (130, 70, 257), (33, 600, 10)]

@@ -128,13 +128,32 @@ def test_automatic_split_binary64(G, shape):
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("shape", [(256, 192, 20000), (1024, 1024, 4096)])
+@pytest.mark.parametrize("shape", [(256, 192, 20000), (1024, 1024, 4096), (1024, 1024, 8192)])
 def test_automatic_split_binary32_deep_k(G, shape):
     m, n, k = shape
     assert G.gemm_plain_ksplit_workspace_size(G.GEMM_F32, m, n, k) > 0
     A, B = inputs.uniform_mnk(m, n, k, 31, dtype=np.float32)
     got = _run(G, A, B, "f32")
     assert oracle.relerr_fro(got, oracle.gemm_omp(A, B)) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(256, 192, 20000), (1024, 1024, 8192), (512, 512, 16384)])
+def test_automatic_split_bf16_deep_k(G, shape):
+    """bfloat16 inputs on the automatic rule's deep-K shapes (4-wave 128 x 128
+    tiles, two per CU, chunks of at least 512): whole-path error against the
+    oracle of the binary32 data <= 2e-2, kernel-only error against the
+    oracle of the rounded inputs <= 1e-5."""
+    m, n, k = shape
+    assert G.gemm_plain_ksplit_workspace_size(G.GEMM_BF16, m, n, k) > 0
+    A, B = inputs.uniform_mnk(m, n, k, 33, dtype=np.float32)
+    got = _run(G, A, B, "bf16")
+    Ar = oracle.bf16_to_f32(oracle.bf16_rne(A))
+    Br = oracle.bf16_to_f32(oracle.bf16_rne(B))
+    e_path = oracle.relerr_fro(got, oracle.gemm_omp(A, B))
+    e_kernel = oracle.relerr_fro(got, oracle.gemm_omp(Ar, Br))
+    say(f"bf16 ksplit {shape}: whole-path {e_path:.3e} kernel-only {e_kernel:.3e}")
+    assert e_path <= TOL["bf16"]
+    assert e_kernel <= 1e-5
 
 
 def test_large_products_run_unsplit_and_leave_workspace(G):

@@ -209,23 +209,30 @@ def test_f32_precision_config(G, n, variant):
     assert np.all(np.abs(left - right) <= 3 * n * 2.0 ** -24 * scale + 1e-30)
 
 
-@pytest.mark.parametrize("n", [2048, 4096])
-def test_bf16_plain_precision_config(G, n):
-    """bfloat16 inputs (RNE of the binary32 data): whole-path error against
-    the binary64 oracle of the binary32 inputs <= 2e-2; kernel-only error
-    against the oracle of the rounded inputs <= 1e-5."""
+@pytest.mark.parametrize("n", [2048, 4096, 8192])
+@pytest.mark.parametrize("variant", ["uniform", "row_scaled"])
+def test_bf16_plain_precision_config(G, n, variant):
+    """bfloat16 inputs (RNE of the binary32 data) at the precision-study sizes,
+    uniform and row-scaled: whole-path error against the binary64 oracle of
+    the binary32 inputs <= 2e-2; kernel-only error against the oracle of the
+    rounded inputs <= 1e-5 (sampled entries)."""
     torch = _torch()
-    A, B = inputs.uniform_square(n, inputs.seed_for(2, n), dtype=np.float32)
+    if variant == "uniform":
+        A, B = inputs.uniform_square(n, inputs.seed_for(2, n), dtype=np.float32)
+    else:
+        A, B = inputs.row_scaled(n, inputs.seed_for(2, n, variant=True))
+    say(f"bf16 precision config n={n} {variant}")
     Ab = dev(A, torch).to(torch.bfloat16)
     Bb = dev(B, torch).to(torch.bfloat16)
     C = G.gemm_plain(Ab, Bb)
     torch.cuda.synchronize()
     Ch = C.cpu().double().numpy()
+    del C
     r, c = sample_idx(n, n, 1500, n + 1)
     err = oracle.relerr_sampled(Ch[r, c], oracle.gemm_entries(A, B, r, c))
     Ar = oracle.bf16_to_f32(oracle.bf16_rne(A))
     Br = oracle.bf16_to_f32(oracle.bf16_rne(B))
     err_k = oracle.relerr_sampled(Ch[r, c], oracle.gemm_entries(Ar, Br, r, c))
-    say(f"bf16 n={n} whole-path relerr={err:.3e} kernel-only={err_k:.3e}")
+    say(f"bf16 n={n} {variant} whole-path relerr={err:.3e} kernel-only={err_k:.3e}")
     assert err <= TOL["bf16"]
     assert err_k <= 1e-5

@@ -102,7 +102,7 @@ def test_split3_n2000_accuracy_ladder(G):
     assert e3 < 0.5 * e2
 
 
-@pytest.mark.parametrize("n", [2048, 4096])
+@pytest.mark.parametrize("n", [2048, 4096, 8192])
 @pytest.mark.parametrize("variant", ["uniform", "row_scaled"])
 def test_split3_precision_config(G, n, variant):
     torch = _torch()
