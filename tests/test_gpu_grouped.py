@@ -134,10 +134,11 @@ def test_plan_update_rejects_misaligned_views(G):
     Ad, Bd = dev(A, torch), dev(B, torch)
     plan = G.GroupedPlan([Ad], [Bd])
     C0 = plan.Cs[0]
-    big = torch.zeros((n, n + 1), dtype=torch.float64, device="cuda:0")
-    big[:, 1:] = Ad
-    view = big[:, 1:]                        # base 8 bytes past a 16-byte boundary
-    assert view.data_ptr() % 16 == 8
+    # same shape and leading dimension, base 8 bytes past a 16-byte boundary
+    flat = torch.zeros(n * n + 1, dtype=torch.float64, device="cuda:0")
+    view = flat[1:].view(n, n)
+    view.copy_(Ad)
+    assert view.data_ptr() % 16 == 8 and view.stride() == Ad.stride()
     with pytest.raises(ValueError, match="16-byte"):
         plan.update([view], [Bd], [torch.empty_like(C0)])
     C0.zero_()
@@ -149,10 +150,11 @@ def test_plan_update_rejects_misaligned_views(G):
     A3, B3 = inputs.uniform_square(m, 506)
     A3d, B3d = dev(A3, torch), dev(B3, torch)
     plan3 = G.GroupedPlan([A3d], [B3d])
-    big3 = torch.zeros((m, m + 1), dtype=torch.float64, device="cuda:0")
-    big3[:, 1:] = A3d
+    flat3 = torch.zeros(m * m + 1, dtype=torch.float64, device="cuda:0")
+    view3 = flat3[1:].view(m, m)
+    view3.copy_(A3d)
     C3 = torch.empty((m, m), dtype=torch.float64, device="cuda:0")
-    plan3.update([big3[:, 1:]], [B3d], [C3])
+    plan3.update([view3], [B3d], [C3])
     plan3.run()
     torch.cuda.synchronize()
     assert oracle.relerr_fro(C3.cpu().numpy(), oracle.gemm(A3, B3)) <= 1e-12
