@@ -110,6 +110,34 @@ int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k,
                       void *stream);
 
 /*
+ * GEMM_NOALLOC_SCRATCH_BYTES -- size of the per-device scratch array of
+ * gemm_plain_ksplit_noalloc (64 MiB; each device the library runs on holds
+ * one until the process ends).
+ */
+#define GEMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * gemm_plain_ksplit_noalloc -- gemm_plain_ksplit for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). Same arguments, product, chunking and
+ * result bits as gemm_plain_ksplit, without the workspace: the partial
+ * products go to a scratch array of GEMM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device. The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); its first call on a device looks
+ * the array's address up once.
+ *   Concurrency: every call on one device shares that device's array, which
+ *   keeps the last call's contents; calls that overlap on one device (other
+ *   streams or threads without ordering) race and give undefined results.
+ *   Order them on one stream or synchronise between them.
+ * Errors: those of gemm_plain, EWORKSPACE when the product's K split needs
+ * more than GEMM_NOALLOC_SCRATCH_BYTES (gemm_plain_ksplit_workspace_size
+ * gives the need), EHIP when the array's address cannot be looked up.
+ */
+int gemm_plain_ksplit_noalloc(int dtype, int64_t m, int64_t n, int64_t k,
+                              const void *A, int64_t lda, const void *B, int64_t ldb,
+                              void *C, int64_t ldc, void *stream);
+
+/*
  * gemm_split_workspace_size -- bytes of device workspace gemm_split needs
  * for this shape (the four bfloat16 operand planes, rows of k rounded up to
  * 8 elements at a pitch rounded up to 64 elements, planes 256-byte aligned).

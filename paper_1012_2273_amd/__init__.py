@@ -156,6 +156,30 @@ def gemm_plain_ksplit(A, B, C=None, workspace=None):
     return C
 
 
+def gemm_plain_ksplit_noalloc(A, B, C):
+    """gemm_plain_ksplit without a workspace, for callers that cannot
+    allocate device memory: the partial products go to the library's
+    per-device scratch array (``_lib.NOALLOC_SCRATCH_BYTES``). ``C`` is the
+    caller's output; the call allocates nothing. Calls that overlap on one
+    device race on the shared array."""
+    code = _dtype_code(A)
+    if B.dtype != A.dtype:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain_ksplit_noalloc", "A and B dtypes differ")
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k:
+        raise GemmArgError(_lib.GEMM_EINVAL, "gemm_plain_ksplit_noalloc",
+                           f"shape mismatch {tuple(A.shape)} x {tuple(B.shape)}")
+    _check_out(C, (m, n), _out_dtype(code), A, "gemm_plain_ksplit_noalloc")
+    pa, lda = _mat(A, "A")
+    pb, ldb = _mat(B, "B")
+    pc, ldc = _mat(C, "C")
+    lib = _lib.load()
+    _lib.check(lib.gemm_plain_ksplit_noalloc(code, m, n, k, pa, lda, pb, ldb, pc, ldc,
+                                             _stream(A)), "gemm_plain_ksplit_noalloc")
+    return C
+
+
 def force_ksplit(parts: int):
     """Split the K loop of this thread's gemm_plain_ksplit calls into
     ``parts`` chunks (-1: automatic). A tuning knob for tests and tools."""

@@ -25,7 +25,11 @@ EXPORTS = (
     "gemm_grouped_plan_update", "gemm_grouped_plan_destroy", "gemm_grouped_plan_info",
     "gemm_grouped", "gemm_strerror", "gemm_last_error", "gemm_tile_config_count",
     "gemm_tile_config_name", "gemm_plain_ksplit_workspace_size", "gemm_plain_ksplit",
+    "gemm_plain_ksplit_noalloc",
 )
+# size of the per-device scratch array of gemm_plain_ksplit_noalloc
+# (GEMM_NOALLOC_SCRATCH_BYTES in the header)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 # the tuning knobs of include/gemm_mi355x_tuning.h (tests and tuning tools)
 TUNING_EXPORTS = ("gemm_tuning_force_tile_config", "gemm_tuning_force_ksplit_parts")
 
@@ -59,6 +63,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
             "gemm_split_workspace_size": (sz, [i64, i64, i64]),
             "gemm_plain_ksplit_workspace_size": (sz, [ci, i64, i64, i64]),
             "gemm_plain_ksplit": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
+            "gemm_plain_ksplit_noalloc": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]),
             "gemm_tuning_force_ksplit_parts": (ci, [ci]),
             "gemm_split_convert": (ci, [i64, i64, vp, i64, ci, vp, vp, i64, vp]),
             "gemm_split": (ci, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),

@@ -357,6 +357,39 @@ static size_t ksplit_bytes(int prec, const KsplitPlan &p, int64_t m, int64_t n) 
   return p.parts <= 1 ? 0 : (size_t)(p.parts - 1) * m * n * (prec == PREC_F64 ? 8 : 4);
 }
 
+// Scratch of the allocation-free K split (gemm_plain_ksplit_noalloc): the
+// partial-product planes live in this array instead of a caller workspace.
+// Each device holds its own copy from the library's load on that device to
+// the end of the process. In host code `scratch` is only a handle for the
+// symbol lookup; its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address reaches kernels.
+// Every chunk writes its whole plane before the sum reads it, so nothing in
+// the array needs clearing between calls.
+static __device__ __attribute__((aligned(256))) char scratch[GEMM_NOALLOC_SCRATCH_BYTES];
+
+static void *scratch_device_address(int *rc) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *rc = hip_fail(e, "hipGetDevice");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void *p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    *rc = e != hipSuccess ? hip_fail(e, "hipGetSymbolAddress(scratch)")
+                          : set_error(GEMM_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+    return nullptr;
+  }
+  addr[dev] = p;
+  return p;
+}
+
 }  // namespace g355
 
 using namespace g355;
@@ -438,10 +471,13 @@ size_t gemm_plain_ksplit_workspace_size(int dtype, int64_t m, int64_t n, int64_t
   return ksplit_bytes(prec, ksplit_plan(prec, m, n, k), m, n);
 }
 
-int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
-                      const void *B, int64_t ldb, void *C, int64_t ldc, void *workspace,
-                      size_t workspace_bytes, void *stream) {
-  clear_error();
+// Validation, plan and launches of the K split, shared by gemm_plain_ksplit
+// (caller workspace) and gemm_plain_ksplit_noalloc (the per-device scratch
+// array below): `ws` is a device address of at least `ws_bytes` bytes, or
+// NULL when `ws_bytes` is 0.
+static int ksplit_product(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                          const void *B, int64_t ldb, void *C, int64_t ldc, void *(*get_ws)(int *),
+                          void *workspace, size_t workspace_bytes, void *stream) {
   if (dtype != GEMM_F64 && dtype != GEMM_F32 && dtype != GEMM_BF16)
     return set_error(GEMM_EUNSUPPORTED, "dtype " + std::to_string(dtype));
   if (m < 0 || n < 0 || k < 0) return set_error(GEMM_EINVAL, "negative size");
@@ -457,12 +493,22 @@ int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k, const void *A,
   const KsplitPlan p = ksplit_plan(prec, m, n, k);
   if (p.parts <= 1) return run_product(prec, LAYOUT_NN, a, es, s);
   const size_t need = ksplit_bytes(prec, p, m, n);
-  if (workspace == nullptr || workspace_bytes < need)
-    return set_error(GEMM_EWORKSPACE, "need " + std::to_string(need) + " bytes, got " +
-                                          std::to_string(workspace_bytes));
-  if ((uintptr_t)workspace % 16 != 0)
-    return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
-  if ((rc = check_ld_range("A", lda, es)) || (rc = check_ld_range("B", ldb, es))) return rc;
+  if (get_ws) {
+    if (need > workspace_bytes)
+      return set_error(GEMM_EWORKSPACE, "the K split of this product needs " +
+                                            std::to_string(need) +
+                                            " bytes of scratch; the allocation-free call holds " +
+                                            std::to_string(workspace_bytes));
+    if ((rc = check_ld_range("A", lda, es)) || (rc = check_ld_range("B", ldb, es))) return rc;
+    if (!(workspace = get_ws(&rc))) return rc;
+  } else {
+    if (workspace == nullptr || workspace_bytes < need)
+      return set_error(GEMM_EWORKSPACE, "need " + std::to_string(need) + " bytes, got " +
+                                            std::to_string(workspace_bytes));
+    if ((uintptr_t)workspace % 16 != 0)
+      return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
+    if ((rc = check_ld_range("A", lda, es)) || (rc = check_ld_range("B", ldb, es))) return rc;
+  }
   const int vw = nn_vector_width(a, es);
   if (!ksplit_offered(prec, LAYOUT_NN, p.cfg, vw))
     return set_error(GEMM_EINVAL, "tile config not offered for the K split");
@@ -471,6 +517,22 @@ int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k, const void *A,
   e = launch_ksplit_sum(prec, C, ldc, workspace, m, n, p.parts - 1, s);
   if (e != hipSuccess) return hip_fail(e, "sum launch");
   return GEMM_OK;
+}
+
+int gemm_plain_ksplit(int dtype, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, void *C, int64_t ldc, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+  clear_error();
+  return ksplit_product(dtype, m, n, k, A, lda, B, ldb, C, ldc, nullptr, workspace,
+                        workspace_bytes, stream);
+}
+
+int gemm_plain_ksplit_noalloc(int dtype, int64_t m, int64_t n, int64_t k, const void *A,
+                              int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
+                              void *stream) {
+  clear_error();
+  return ksplit_product(dtype, m, n, k, A, lda, B, ldb, C, ldc, scratch_device_address, nullptr,
+                        GEMM_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 static void split_layout(int np, int64_t m, int64_t n, int64_t k, int64_t &kp, int64_t &ldp,

@@ -218,6 +218,33 @@ def test_ksplit_workspace_and_validation(lib):
     assert call(m=0, A=None, C=None) == _lib.GEMM_OK
 
 
+def test_ksplit_noalloc_validation(lib):
+    """The allocation-free K split checks its arguments like the workspace
+    call and refuses, before touching a device, a product whose K split needs
+    more than the per-device scratch array holds."""
+    v = ctypes.c_void_p
+    F64 = _lib.GEMM_F64
+    size = lib.gemm_plain_ksplit_workspace_size
+
+    def call(dtype=F64, m=1024, n=1024, k=8192, A=v(256), lda=8192, B=v(256), ldb=1024,
+             C=v(256), ldc=1024):
+        return lib.gemm_plain_ksplit_noalloc(dtype, m, n, k, A, lda, B, ldb, C, ldc, None)
+
+    assert lib.gemm_tuning_force_ksplit_parts(20) == _lib.GEMM_OK
+    try:
+        # 20 chunks asked: 410 rounded up to 448 indices, so 19 chunks and 18 planes
+        assert size(F64, 1024, 1024, 8192) == 18 * 1024 * 1024 * 8 > _lib.NOALLOC_SCRATCH_BYTES
+        assert call() == _lib.GEMM_EWORKSPACE
+        assert b"scratch" in lib.gemm_last_error()
+    finally:
+        assert lib.gemm_tuning_force_ksplit_parts(-1) == _lib.GEMM_OK
+    assert call(dtype=9) == _lib.GEMM_EUNSUPPORTED
+    assert call(k=-1) == _lib.GEMM_EINVAL
+    assert call(B=None) == _lib.GEMM_ENULL
+    assert call(ldc=1000) == _lib.GEMM_ELD
+    assert call(m=0, A=None, C=None) == _lib.GEMM_OK
+
+
 def test_backward_validation(lib):
     v = ctypes.c_void_p
     assert lib.gemm_backward(5, 4, 4, 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, v(16), 4, None) == _lib.GEMM_EUNSUPPORTED
