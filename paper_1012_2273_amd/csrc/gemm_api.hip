@@ -48,6 +48,8 @@ static thread_local int t_force_parts = -1;
 // The 128x256w8 shape is offered to the bfloat16-MFMA products only.
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
+  if (cfg == CFG_128x128_K2)   // every precision (16-bit: direct-to-LDS only)
+    return true;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
   if (cfg == CFG_64x64_K4) return prec == PREC_F64;

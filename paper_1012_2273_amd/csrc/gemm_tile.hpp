@@ -193,6 +193,8 @@ template <int P, class S> __host__ __device__ constexpr int bk_of() {
     constexpr bool even16 = (S::BM * 16 * 4 / 1024) % waves == 0 && (S::BN * 16 * 4 / 1024) % waves == 0;
     constexpr bool big4 = S::NT == 256 && S::BM * S::BN >= 128 * 128;
     return even16 && !big4 ? 16 : 32;
+  } else if constexpr (P == PREC_BF16 && S::KS > 1) {
+    return 64;
   } else if constexpr (P == PREC_BF16 && S::NT >= 512 && S::BM * S::BN == 128 * 128) {
     return G355_BF16_W8_BK;
   } else {

@@ -211,8 +211,9 @@ struct DmaOp {
         const char *p = region + k * RB + ((cc ^ swzm(k)) * 16) + ce * ES;
         const s16x4 t = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
             (__attribute__((address_space(3))) s16x4 *)(p));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v.e[4 * h + j] = (E)t[j];
+        // whole 8 bytes at once: element-wise 16-bit inserts made the
+        // compiler wait for each read right after issuing it
+        __builtin_memcpy(&v.e[4 * h], &t, 8);
       }
     } else {
       const int cc = row / V, ce = row % V;
@@ -262,6 +263,11 @@ constexpr int kRing16 = G355_RING16_KB * 1024;
 #ifndef G355_RING16_W8_KB
 #define G355_RING16_W8_KB 48
 #endif
+// The 16-bit 128 x 128 tile with the K-tile split between wave pairs holds
+// one workgroup per CU: its ring takes most of the LDS.
+#ifndef G355_RING16_K2_KB
+#define G355_RING16_K2_KB 128
+#endif
 
 // Wait until at most n K-tiles of DPW transfers each are still in flight
 // (0 <= n <= MAXT; n is the same on every lane).
@@ -310,7 +316,9 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   // workgroup), and 144 KiB of the 160 KiB LDS for 8-wave shapes. 16-bit: as
   // many stages as fit in the 16-bit ring budget (2 to 8). vmcnt (6 bits)
   // bounds the transfers a wave may leave outstanding.
-  static constexpr int R16 = (S::NT >= 512 && S::BM * S::BN <= 128 * 128) ? G355_RING16_W8_KB * 1024 : kRing16;
+  static constexpr int R16 = S::KS > 1 ? G355_RING16_K2_KB * 1024
+                             : (S::NT >= 512 && S::BM * S::BN <= 128 * 128) ? G355_RING16_W8_KB * 1024
+                                                                           : kRing16;
   static constexpr int FIT = (T::KPL == 8 ? R16 : (S::NT <= 256 ? 72 : 144) * 1024) / STAGE;
   static constexpr int VMAX = 1 + 63 / (PER_WAVE > 0 ? PER_WAVE : 1);
   static constexpr int NS0 = T::KPL == 8 ? (FIT < 8 ? FIT : 8) : (FIT >= 3 ? 3 : 2);

@@ -126,7 +126,23 @@ template <int P, class S, bool TA, bool TB, class F> static int by_width(int vw,
 }
 
 template <int P, class S, class F> static int by_layout(int layout, int vw, F &f) {
-  if constexpr (!shape_ok<P, S>()) {
+  if constexpr (P == PREC_BF16 && S::KS > 1) {
+    // 16-bit K-split tiles exist on the direct-to-LDS path only (64-deep
+    // K-tiles; the register path's 32-deep tiles do not split)
+    if (vw != 16) return -1;
+    switch (layout) {
+      case LAYOUT_NN:
+        if constexpr (dma_ok<P, S, false, false>()) return f(KTag<P, S, false, false, 16>{});
+        return -1;
+      case LAYOUT_NT:
+        if constexpr (dma_ok<P, S, false, true>()) return f(KTag<P, S, false, true, 16>{});
+        return -1;
+      case LAYOUT_TN:
+        if constexpr (dma_ok<P, S, true, false>()) return f(KTag<P, S, true, false, 16>{});
+        return -1;
+    }
+    return -1;
+  } else if constexpr (!shape_ok<P, S>()) {
     return -1;   // not offered for this precision (the host never picks it)
   } else if constexpr (P == PREC_SPLIT || P == PREC_SPLIT3) {
     // the split planes are always written K-contiguous and 16-byte aligned
