@@ -18,12 +18,15 @@ seeded synthetic inputs:
 Each path is bracketed by HIP events on torch's current stream (the stream
 the kernels run on); the step loop is bracketed by device synchronisation.
 ``value`` is the binary64 rate 2N^3/t at N = 2000; the split rate and every
-other path are reported beside it with their normwise error against the host
-binary64 BLAS product of the same inputs (the tests hold every path to the
-oracle; the bench calls the oracle only in its CPU-baseline leg).
-``roofline`` describes the binary64 kernel (MFMA bound); ``cpu_baseline``
-times the oracle (the paper's Algorithm 4 loop on all host
-threads) on the same N = 2000 binary64 product.
+other path are reported beside it with their normwise error against the
+oracle's product of the same inputs. The oracle runs only in the CPU-baseline
+leg: that leg times it (the paper's Algorithm 4 loop on all host threads) on
+the N = 2000 binary64 product, keeps that product as the binary64 reference,
+runs it once more on the binary32 inputs for the binary32, bfloat16 and split
+paths, and serves every other stated error (full products up to 8.1e9
+multiply-adds, 2000 sampled entries beyond). With --no-cpu-baseline the errors
+fall back to host BLAS and ``rel_err_reference`` says so.
+``roofline`` describes the binary64 kernel (MFMA bound).
 
 Outside the timed step loop (each skippable):
   sweep     binary64 at the paper's sizes N = 10 ... 2000 plus 4096: median
@@ -32,8 +35,11 @@ Outside the timed step loop (each skippable):
             and six rectangular binary64 shapes (m x k times k x n)
   transfer  N = 2000 binary64 with the operands on the host (pinned): H2D of
             A and B, the product, D2H of C, timed together (never ``value``)
-  host      the host CPU, the single-thread oracle at N = 500 and the
-            Algorithm 4 loop on two threads at N = 2000 (the paper's two cores)
+  host      the host CPU (model, sockets, cores, threads), the single-thread
+            oracle at N = 10 ... 2000, the Algorithm 4 loop on all host
+            threads at N = 10 ... 2000 (4096 with --host-n4096) and on two
+            threads at N = 2000 (the paper's two cores), with the GPU's
+            binary64 speedup over each
 """
 from __future__ import annotations
 
@@ -107,15 +113,53 @@ def _entries(A, B, r, c):
     return np.einsum("ij,ji->i", A[r, :], B[:, c])
 
 
+class ErrRef:
+    """Normwise relative error of a device result against a host product of
+    the exact inputs. With the oracle (the CPU-baseline leg): its full product
+    on all host threads up to FULL_LIMIT multiply-adds, its entries on a
+    sample of 2000 positions beyond. Without it: host binary64 BLAS."""
+    FULL_LIMIT = 8.1e9      # N = 2000 squares in full
+
+    def __init__(self, oracle=None, threads=1):
+        self.o, self.thr = oracle, threads
+        if oracle is not None:
+            self.kind = ("normwise, against the oracle's binary64 product of the same inputs "
+                         f"(full product on {threads} host threads up to 8.1e9 multiply-adds, "
+                         "2000 sampled entries beyond)")
+        else:
+            self.kind = ("normwise, against the host binary64 BLAS product of the same inputs "
+                         "(the CPU-baseline leg, which holds the oracle, was skipped)")
+
+    def product(self, A, B):
+        return self.o.gemm_omp(A, B, self.thr) if self.o is not None else _blas(A, B)
+
+    def err(self, C, A, B, full=None, seed=0):
+        """C: device result on the host (the full matrix)."""
+        if full is not None:
+            return _relerr(C, full)
+        m, k = A.shape
+        n = B.shape[1]
+        if self.o is None or float(m) * n * k <= self.FULL_LIMIT:
+            return _relerr(C, self.product(A, B))
+        g = np.random.Generator(np.random.PCG64(seed))
+        r = g.integers(0, m, 2000)
+        c = g.integers(0, n, 2000)
+        return _relerr(np.asarray(C, np.float64)[r, c], self.o.gemm_entries(A, B, r, c))
+
+    def entries(self, A, B, r, c):
+        return self.o.gemm_entries(A, B, r, c) if self.o is not None else _entries(A, B, r, c)
+
+
 def _median_ms(pairs):
     return float(np.median([a.elapsed_time(b) for a, b in pairs]))
 
 
-def fp64_sweep(G, torch, dev, stream, inputs, check):
+def fp64_sweep(G, torch, dev, stream, inputs, ref, full=None):
     """The paper's size sweep (Tables 1-2: N = 100 ... 2000) plus N = 10 and
     4096, binary64, inputs resident."""
     out = {}
     for n in (10, 100, 500, 1000, 2000, 4096):
+        print(f"sweep: binary64 N={n}", file=sys.stderr, flush=True)
         A, B = inputs.uniform_square(n, inputs.seed_for(1, n))
         Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
         Cd = torch.empty((n, n), dtype=torch.float64, device=dev)
@@ -155,9 +199,9 @@ def fp64_sweep(G, torch, dev, stream, inputs, check):
             d["amortised_us"] = round(per * 1e6, 3)
             d["amortised_gflops"] = round(2.0 * n ** 3 / per / 1e9, 3)
             d["amortised_gbs"] = round(24.0 * n * n / per / 1e9, 2)   # A, B, C once
-        if check:
+        if ref is not None:
             C = Cd.cpu().numpy()
-            d["rel_err"] = float(f"{_relerr(C, _blas(A, B)):.3e}")
+            d["rel_err"] = float(f"{ref.err(C, A, B, full=(full or {}).get(n)):.3e}")
         out[str(n)] = d
         del Ad, Bd, Cd
     return out
@@ -189,22 +233,25 @@ def _median_call_ms(fn, torch, stream):
     return _median_ms(pairs)
 
 
-def rect_sweep(G, torch, dev, stream, inputs, check):
+def rect_sweep(G, torch, dev, stream, inputs, ref):
     """Rectangular binary64 products (m x k times k x n, the paper's problem
     statement), median per-call rate after >= 30 ms of warm-up; where
     gemm_plain_ksplit splits the K loop (too few output tiles for the
     device), its rate beside it ("ksplit")."""
     out = {}
     for m, n, k in RECT_SHAPES:
+        print(f"sweep: binary64 {m}x{n}x{k}", file=sys.stderr, flush=True)
         A, B = inputs.uniform_mnk(m, n, k, 5_000_000 + m + n + k)
         Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
         Cd = torch.empty((m, n), dtype=torch.float64, device=dev)
         t = _median_call_ms(lambda: G.gemm_plain(Ad, Bd, Cd), torch, stream) * 1e-3
         d = {"ms": round(t * 1e3, 5), "gflops": round(2.0 * m * n * k / t / 1e9, 2),
              "frac_peak": round(2.0 * m * n * k / t / 1e12 / PEAK["f64"], 4)}
-        ref = _blas(A, B) if check else None
-        if check:
-            d["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), ref):.3e}")
+        full = None
+        if ref is not None:
+            if ref.o is None or float(m) * n * k <= ref.FULL_LIMIT:
+                full = ref.product(A, B)
+            d["rel_err"] = float(f"{ref.err(Cd.cpu().numpy(), A, B, full=full, seed=m + n):.3e}")
         need = G.gemm_plain_ksplit_workspace_size(G.GEMM_F64, m, n, k)
         if need > 0:
             ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -212,8 +259,8 @@ def rect_sweep(G, torch, dev, stream, inputs, check):
             ks = {"ms": round(tk * 1e3, 5), "gflops": round(2.0 * m * n * k / tk / 1e9, 2),
                   "frac_peak": round(2.0 * m * n * k / tk / 1e12 / PEAK["f64"], 4),
                   "workspace_bytes": need}
-            if check:
-                ks["rel_err"] = float(f"{_relerr(Cd.cpu().numpy(), ref):.3e}")
+            if ref is not None:
+                ks["rel_err"] = float(f"{ref.err(Cd.cpu().numpy(), A, B, full=full, seed=m + n):.3e}")
             d["ksplit"] = ks
             del ws
         out[f"{m}x{n}x{k}"] = d
@@ -258,29 +305,80 @@ def transfer_inclusive(G, torch, dev, stream, A, B, C_resident, reps=10):
             "matches_resident": bool(torch.equal(Ch, C_resident.cpu()))}
 
 
-def host_info(oracle, inputs):
-    """The host CPU, the single-thread oracle at N = 500 and the paper's
-    Algorithm 4 on two threads at N = 2000."""
-    model = None
+def lscpu():
+    """Host CPU model, sockets, cores per socket, threads per core and CPU
+    count from lscpu (else /proc/cpuinfo), and the threads this process may use."""
+    info = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket":
+                "cores_per_socket", "Thread(s) per core": "threads_per_core", "CPU(s)": "cpus"}
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys and keys[k.strip()] not in info:
+                v = v.strip()
+                info[keys[k.strip()]] = int(v) if v.isdigit() else v
+    except (OSError, ValueError):
         pass
-    A, B = inputs.uniform_square(500, inputs.seed_for(0, 500))
-    t0 = time.perf_counter()
-    oracle.gemm(A, B)
-    t1 = time.perf_counter() - t0
-    A, B = inputs.uniform_square(2000, inputs.seed_for(1, 2000))
-    t0 = time.perf_counter()
-    oracle.gemm_omp(A, B, 2)
-    t2 = time.perf_counter() - t0
-    return {"cpu": model, "threads_available": host_threads(),
-            "oracle_1thread_n500": {"s": round(t1, 3), "gflops": round(2.0 * 500 ** 3 / t1 / 1e9, 3)},
-            "alg4_2threads_n2000": {"s": round(t2, 3), "gflops": round(2.0 * 2000 ** 3 / t2 / 1e9, 3)}}
+    if "model" not in info:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["model"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    info["threads_available"] = host_threads()
+    return info
+
+
+def _host_time(fn, min_s=0.05):
+    """Median wall time of fn() over repeats totalling at least min_s."""
+    runs = []
+    t_end = time.perf_counter() + min_s
+    while not runs or (time.perf_counter() < t_end and len(runs) < 1000):
+        t0 = time.perf_counter()
+        fn()
+        runs.append(time.perf_counter() - t0)
+    return float(np.median(runs))
+
+
+def host_info(oracle, inputs, gpu_sweep=None, alg4_sizes=(10, 100, 500, 1000, 2000)):
+    """The host CPU and the paper's CPU programs on it: the oracle on one
+    thread at the paper's sizes N = 10 ... 2000, the paper's Algorithm 4 (rows
+    split statically over threads) on all host threads at N = 10 ... 2000 (and
+    4096 with --host-n4096: the loop walks B by columns, which at N = 4096 no
+    longer fits the host caches and takes minutes) and on two threads at
+    N = 2000 (the paper's two cores). Inputs are made before the
+    clock starts, as the paper times only the product. Rates at 2N^3 and at the
+    paper's N^2(2N-1) count; ``gpu_speedup`` is the host time over the GPU's
+    binary64 time at the same N (the sweep's median per call)."""
+    thr = host_threads()
+
+    t_host0 = time.perf_counter()
+
+    def row(n, threads):
+        print(f"host: N={n} on {threads} thread(s) "
+              f"({time.perf_counter() - t_host0:.1f} s into the host sweep)", file=sys.stderr,
+              flush=True)
+        A, B = inputs.uniform_square(n, inputs.seed_for(1, n))
+        if threads == 1:
+            t = _host_time(lambda: oracle.gemm(A, B))
+        else:
+            t = _host_time(lambda: oracle.gemm_omp(A, B, threads))
+        d = {"s": float(f"{t:.4g}"), "gflops": round(2.0 * n ** 3 / t / 1e9, 3),
+             "gflops_paper_count": round(n * n * (2 * n - 1) / t / 1e9, 3)}
+        g = (gpu_sweep or {}).get(str(n))
+        if g:
+            d["gpu_speedup"] = round(t / (g["ms"] * 1e-3), 1)
+        return d
+
+    return {"cpu": lscpu(),
+            "oracle_1thread": {str(n): row(n, 1) for n in (10, 100, 500, 1000, 2000)},
+            f"alg4_{thr}threads": {str(n): row(n, thr) for n in alg4_sizes},
+            "alg4_2threads": {"2000": row(2000, 2)}}
 
 
 def main():
@@ -296,6 +394,9 @@ def main():
                     help="force one tile configuration id for single-product launches")
     ap.add_argument("--no-sweep", action="store_true", help="skip the binary64 size sweep")
     ap.add_argument("--no-transfer", action="store_true", help="skip the host-buffer timing")
+    ap.add_argument("--host-n4096", action="store_true",
+                    help="also time the paper's Algorithm 4 on all host threads at N = 4096 "
+                         "(several minutes of host work)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device-to-device copy of 512 MiB (3 times) so that "
                          "counter runs can scale FETCH_SIZE/WRITE_SIZE to bytes")
@@ -396,6 +497,7 @@ def main():
 
     # ---------------------------------------------------------------- timing
     stream = torch.cuda.current_stream(dev)
+    log(f"timing: {args.warmup} warm-up and {args.steps} timed steps of {order}")
     for _ in range(args.warmup):
         for p in order:
             work[p][0]()
@@ -437,15 +539,46 @@ def main():
         loop[gpath] = float(np.mean([a.elapsed_time(b) for a, b in le]))
         del gC
 
-    # ---------------------------------------------------------- error check
-    # against the host binary64 BLAS product of the same inputs
-    errs = {}
-    if not args.no_check:
+    # ---------------------------------------------------------- cpu baseline
+    # The CPU-baseline leg: the oracle timed on the host cores, and the
+    # reference products every stated error is taken against.
+    cpu = None
+    ref = None
+    ref64 = None
+    if not args.no_cpu_baseline:
+        import oracle
+        thr = host_threads()
+        log(f"cpu baseline: oracle N={N} on {thr} threads, about 10 s")
+        ref = ErrRef(oracle, thr)
         A, B = host["fp64"]
-        errs["fp64"] = _relerr(C64d.cpu().numpy(), _blas(A, B))
+        runs = []
+        t_start = time.perf_counter()
+        # repeat the full product for about 10 s of host work (at least 3 runs)
+        while len(runs) < 3 or (time.perf_counter() - t_start < 10.0 and len(runs) < 200):
+            t0 = time.perf_counter()
+            ref64 = oracle.gemm_omp(A, B, thr)
+            runs.append(time.perf_counter() - t0)
+        tc = float(np.median(runs))
+        cpu = {"value": round(2.0 * N ** 3 / tc / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
+               "kind": "oracle",
+               "sample": f"the full N={N} binary64 product, oracle loop (row, column, "
+                         f"reduction; no FMA) with rows split statically over {thr} threads "
+                         f"as in the paper's Algorithm 4; median of {len(runs)} runs "
+                         f"({sum(runs):.1f} s of host work), {tc:.2f} s each"}
+    elif not args.no_check:
+        ref = ErrRef(None)
+    if args.no_check:
+        ref = None
+
+    # ---------------------------------------------------------- error check
+    errs = {}
+    if ref is not None:
+        log("errors against the reference products")
+        A, B = host["fp64"]
+        errs["fp64"] = ref.err(C64d.cpu().numpy(), A, B, full=ref64)
         if "f32" in host:
             A, B = host["f32"]
-            ref32 = _blas(A, B)
+            ref32 = ref.product(A, B)       # one oracle run on the binary32 inputs
             if "split" in order:
                 errs["split"] = _relerr(Csd.cpu().double().numpy(), ref32)
             if "split3" in order:
@@ -454,14 +587,15 @@ def main():
                 errs["fp32"] = _relerr(C32d.cpu().double().numpy(), ref32)
             if "bf16" in order:
                 errs["bf16"] = _relerr(C16d.cpu().double().numpy(), ref32)
+            del ref32
         if "backward" in order:
             Ab, Bb, Wb = host["backward"]
             g = np.random.Generator(np.random.PCG64(1))
             r = g.integers(0, Ab.shape[0], 400)
             c = g.integers(0, Ab.shape[0], 400)
             dA, dB = (t.cpu().double().numpy() for t in bw_out["d"])
-            eA = _relerr(dA[r, c], _entries(Wb, Bb.T, r, c))
-            eB = _relerr(dB[r, c], _entries(Ab.T, Wb, r, c))
+            eA = _relerr(dA[r, c], ref.entries(Wb, np.ascontiguousarray(Bb.T), r, c))
+            eB = _relerr(dB[r, c], ref.entries(np.ascontiguousarray(Ab.T), Wb, r, c))
             errs["backward"] = max(eA, eB)
         for gpath, gd in gp.items():
             worst = 0.0
@@ -472,35 +606,14 @@ def main():
                 r = g.integers(0, n, 40)
                 c = g.integers(0, n, 40)
                 got = gd["plan"].Cs[i].cpu().double().numpy()[r, c]
-                worst = max(worst, _relerr(got, _entries(A, B, r, c)))
+                worst = max(worst, _relerr(got, ref.entries(A, B, r, c)))
             errs[gpath] = worst
-
-    # ---------------------------------------------------------- cpu baseline
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        thr = host_threads()
-        A, B = host["fp64"]
-        runs = []
-        t_start = time.perf_counter()
-        # repeat the full product for about 10 s of host work (at least 3 runs)
-        while len(runs) < 3 or (time.perf_counter() - t_start < 10.0 and len(runs) < 200):
-            t0 = time.perf_counter()
-            oracle.gemm_omp(A, B, thr)
-            runs.append(time.perf_counter() - t0)
-        tc = float(np.median(runs))
-        cpu = {"value": round(2.0 * N ** 3 / tc / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
-               "kind": "oracle",
-               "sample": f"the full N={N} binary64 product, oracle loop (row, column, "
-                         f"reduction; no FMA) with rows split statically over {thr} threads "
-                         f"as in the paper's Algorithm 4; median of {len(runs)} runs "
-                         f"({sum(runs):.1f} s of host work), {tc:.2f} s each"}
 
     # ------------------------------------------- outside the timed step loop
     sweep = rect = None
     if not args.no_sweep:
-        sweep = fp64_sweep(G, torch, dev, stream, inputs, not args.no_check)
-        rect = rect_sweep(G, torch, dev, stream, inputs, not args.no_check)
+        sweep = fp64_sweep(G, torch, dev, stream, inputs, ref, full={N: ref64})
+        rect = rect_sweep(G, torch, dev, stream, inputs, ref)
     xfer = None
     if not args.no_transfer:
         A, B = host["fp64"]
@@ -508,7 +621,8 @@ def main():
     hinfo = None
     if not args.no_cpu_baseline:
         import oracle     # the CPU-baseline leg: the oracle timed on the host
-        hinfo = host_info(oracle, inputs)
+        hinfo = host_info(oracle, inputs, sweep,
+                          (10, 100, 500, 1000, 2000) + ((4096,) if args.host_n4096 else ()))
 
     # ---------------------------------------------------------- report
     paths_out = {}
@@ -551,7 +665,7 @@ def main():
                        "vs_fp64": (round(ms["fp64"] / ms["split"], 2)
                                  if "split" in ms and "fp64" in ms else None)},
         "fp64_rel_err": paths_out.get("fp64", {}).get("rel_err"),
-        "rel_err_reference": "normwise, against the host binary64 BLAS product of the same inputs",
+        "rel_err_reference": ref.kind if ref is not None else None,
         "paths": paths_out,
         "roofline": ({"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"],
                       "unit": "TFLOP/s", "frac": round(achieved / PEAK["f64"], 4),

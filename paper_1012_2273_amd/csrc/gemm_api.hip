@@ -35,7 +35,7 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
                                          {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
                                          {128, 64, "128x64k2"},   {64, 64, "64x64k2"},
                                          {32, 32, "32x32k2"},     {128, 256, "128x256w8"},
-                                         {64, 64, "64x64k4"}};
+                                         {64, 64, "64x64k4"},     {128, 128, "128x128k2ld"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 // Tuning knobs (gemm_mi355x_tuning.h): per calling thread, so a test or a
@@ -48,7 +48,7 @@ static thread_local int t_force_parts = -1;
 // The 128x256w8 shape is offered to the bfloat16-MFMA products only.
 bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
-  if (cfg == CFG_128x128_K2)   // every precision (16-bit: direct-to-LDS only)
+  if (cfg == CFG_128x128_K2 || cfg == CFG_128x128_K2_LD)   // 16-bit, loaders: direct-to-LDS only
     return true;
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
@@ -116,9 +116,13 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
       return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
     case PREC_BF16:
       if (t128 >= 2 * cus) return CFG_128x256_W8;
-      if (t128 >= big) return CFG_128x128_W8;
+      if (t128 >= big) return CFG_128x128_K2_LD;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
-    default:  // split, two or three planes
+    case PREC_SPLIT:
+      if (t128 >= 2 * cus) return CFG_128x256_W8;
+      if (t128 >= big) return CFG_128x128_K2_LD;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+    default:  // three planes, fused splits
       if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
@@ -195,7 +199,11 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   if (forced >= 0 && forced < CFG_COUNT && cfg_supported(prec, forced) &&
       plain_offered(prec, layout, forced, vw))
     return forced;
-  const int pick = choose_rule(prec, m, n);
+  int pick = choose_rule(prec, m, n);
+  // shapes offered on the direct-to-LDS path only (loader waves, 16-bit K
+  // split) step back to the 8-wave tile where the operands need the
+  // register path or the layout has no such kernel
+  if (!plain_offered(prec, layout, pick, vw)) pick = CFG_128x128_W8;
   if (prec != PREC_F64 && prec != PREC_F32) return pick;
   const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
   if (kCfgs[pick].bm < 128 || shape_rate(prec, pick) <= 0.0) return pick;

@@ -165,10 +165,13 @@ struct GemmArgs {
 // Tile shape: BM x BN outputs per workgroup, WM x WN wave positions (64
 // lanes each), KS waves per position splitting every K-tile between them
 // (their partial sums are added through LDS at the end of the tile); KB > 0
-// fixes the K-tile depth of the direct-to-LDS path (else bk_of's rule).
-template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1, int KB_ = 0> struct Shape {
-  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KS = KS_, KB = KB_;
-  static constexpr int NT = 64 * WM * WN * KS;
+// fixes the K-tile depth of the direct-to-LDS path (else bk_of's rule);
+// LDW > 0 adds that many loader waves, which issue every operand transfer of
+// the direct-to-LDS path and no MFMA (the other waves then only compute).
+template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1, int KB_ = 0, int LDW_ = 0> struct Shape {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, KS = KS_, KB = KB_, LDW = LDW_;
+  static constexpr int NC = 64 * WM * WN * KS;   // compute threads
+  static constexpr int NT = NC + 64 * LDW;
   static constexpr int WTM = BM / WM, WTN = BN / WN;   // per-wave tile
   static constexpr int FM = WTM / 16, FN = WTN / 16;   // 16x16 blocks per wave
   static_assert(FM >= 1 && FN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "bad shape");

@@ -302,7 +302,8 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   static constexpr int NW = S::NT / 64, BKD = bk_of<P, S>();
   static constexpr int TR_A = S::BM * BKD * ES / 1024, TR_B = S::BN * BKD * ES / 1024;
   static constexpr bool whole(int w) { return w >= 1 && TR_A % w == 0 && TR_B % w == 0; }
-  static constexpr int LW = whole(NW) ? NW : whole(NW / 2) ? NW / 2 : whole(NW / 4) ? NW / 4 : NW;
+  static constexpr int LW = S::LDW > 0 ? S::LDW
+                            : whole(NW) ? NW : whole(NW / 2) ? NW / 2 : whole(NW / 4) ? NW / 4 : NW;
   static constexpr int LT = 64 * LW;
   using OA = DmaOp<E, S::BM, BKD, LT, !TA, Geom<P, S>::KG, Geom<P, S>::MB, ILA * ES == 16>;
   using OB = DmaOp<E, S::BN, BKD, LT, TB, Geom<P, S>::KG, Geom<P, S>::MB, ILB * ES == 16>;
@@ -325,7 +326,7 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   static constexpr int NS1 = NS0 < VMAX ? NS0 : VMAX;
   static constexpr int NS = NS1 < 2 ? 2 : NS1;
   static constexpr bool OK = OA::OK && OB::OK && Geom<P, S>::OK && PER_WAVE < 32 &&
-                             NS * STAGE <= 160 * 1024;
+                             NS * STAGE <= 160 * 1024 && (S::LDW == 0 || whole(S::LDW));
 };
 
 template <int P, class S, bool TA, bool TB> __host__ __device__ constexpr bool dma_ok() {
@@ -398,15 +399,21 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   const int wm = wpos % S::WM, wn = wpos / S::WM;
   const int lr = lane % MB, lgp = lane / MB;
 
-  const bool loader = Plan::LW == S::NT / 64 || wave < Plan::LW;   // waves that issue transfers
+  // Waves that issue transfers: the loader waves of a shape that has them
+  // (the others only compute), else all waves or the first LW of them.
+  constexpr bool SPEC = S::LDW > 0;
+  constexpr int CW = S::WM * S::WN * S::KS;     // compute waves
+  const bool is_ld = SPEC && wave >= CW;
+  const int lwave = SPEC ? (is_ld ? wave - CW : 0) : wave;   // index among the loaders
+  const bool loader = SPEC ? is_ld : (Plan::LW == S::NT / 64 || wave < Plan::LW);
   const E *Ap[3] = {reinterpret_cast<const E *>(g.A), reinterpret_cast<const E *>(g.A2),
                     reinterpret_cast<const E *>(g.A3)};
   const E *Bp[3] = {reinterpret_cast<const E *>(g.B), reinterpret_cast<const E *>(g.B2),
                     reinterpret_cast<const E *>(g.B3)};
   OA oa;
   OB ob;
-  oa.init(g.lda, m0, g.M, wave, lane);
-  ob.init(g.ldb, n0, g.N, wave, lane);
+  oa.init(g.lda, m0, g.M, lwave, lane);
+  ob.init(g.ldb, n0, g.N, lwave, lane);
 
   // region of plane pl of operand A / B in stage st
   auto regA = [&](int st, int pl) { return smem + st * STAGE + pl * OA::BYTES; };
@@ -420,8 +427,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     for (int pl = 0; pl < PL; ++pl) {
       const E *ta = TA ? Ap[pl] + k0 * g.lda + m0 : Ap[pl] + m0 * g.lda + k0;
       const E *tb = TB ? Bp[pl] + n0 * g.ldb + k0 : Bp[pl] + k0 * g.ldb + n0;
-      oa.issue(ta, k0, g.K, regA(st, pl), wave);
-      ob.issue(tb, k0, g.K, regB(st, pl), wave);
+      oa.issue(ta, k0, g.K, regA(st, pl), lwave);
+      ob.issue(tb, k0, g.K, regB(st, pl), lwave);
     }
   };
 
@@ -546,15 +553,15 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     constexpr int pl = k / per_plane, r = k % per_plane;
     if (pend.on && loader) {
       if constexpr (r < OA::PERW)
-        oa.issue_one(r, pend.sa[pl], pend.krem, pend.la[pl], wave);
+        oa.issue_one(r, pend.sa[pl], pend.krem, pend.la[pl], lwave);
       else
-        ob.issue_one(r - OA::PERW, pend.sb[pl], pend.krem, pend.lb[pl], wave);
+        ob.issue_one(r - OA::PERW, pend.sb[pl], pend.krem, pend.lb[pl], lwave);
     }
   };
   // pre-barrier MFMA number n: issue every transfer k with k * NPRE / (2 DPW) == n
   auto maybe_issue = [&](auto n_tag) {
     constexpr int n = decltype(n_tag)::value;
-    if constexpr (BURST) return;
+    if constexpr (BURST || SPEC) return;
     [&]<int... k>(std::integer_sequence<int, k...>) {
       ((void)((k * NPRE / (2 * DPW) == n) ? (issue_k(std::integral_constant<int, k>{}), 0) : 0), ...);
     }(std::make_integer_sequence<int, DPW>{});
@@ -593,8 +600,8 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   auto ktile = [&](auto p0_tag, int64_t kt, int cur) {
     constexpr int P0 = decltype(p0_tag)::value;
     const int nxt = cur + 1 == NS ? 0 : cur + 1;
-    prep_tile(kt + D, cur == 0 ? NS - 1 : cur - 1);
-    if constexpr (BURST) {
+    if constexpr (!SPEC) prep_tile(kt + D, cur == 0 ? NS - 1 : cur - 1);
+    if constexpr (BURST && !SPEC) {
       [&]<int... k>(std::integer_sequence<int, k...>) {
         (issue_k(std::integral_constant<int, k>{}), ...);
       }(std::make_integer_sequence<int, DPW>{});
@@ -623,30 +630,94 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
       if (t < KT) issue_tile(t, t);
     wait_tiles<DPW, D - 1>(KT < D ? (int)KT - 1 : D - 1);   // tile 0 has landed
     raw_barrier();
-    read_unit(0, 0, I0{});
-    int st = 0;
-    if constexpr (U % 2 == 0) {
-      for (int64_t kt = 0; kt < KT; ++kt) {
-        ktile(I0{}, kt, st);
-        st = st + 1 == NS ? 0 : st + 1;
-      }
-    } else {
-      for (int64_t kt = 0; kt < KT; kt += 2) {
-        ktile(I0{}, kt, st);
-        st = st + 1 == NS ? 0 : st + 1;
-        if (kt + 1 < KT) {
-          ktile(std::integral_constant<int, 1>{}, kt + 1, st);
+    auto compute_loop = [&] {
+      read_unit(0, 0, I0{});
+      int st = 0;
+      if constexpr (U % 2 == 0) {
+        for (int64_t kt = 0; kt < KT; ++kt) {
+          ktile(I0{}, kt, st);
           st = st + 1 == NS ? 0 : st + 1;
         }
+      } else {
+        for (int64_t kt = 0; kt < KT; kt += 2) {
+          ktile(I0{}, kt, st);
+          st = st + 1 == NS ? 0 : st + 1;
+          if (kt + 1 < KT) {
+            ktile(std::integral_constant<int, 1>{}, kt + 1, st);
+            st = st + 1 == NS ? 0 : st + 1;
+          }
+        }
       }
+    };
+    if constexpr (SPEC) {
+      if (is_ld) {
+        // loader waves: per K-tile, the transfers of the tile D ahead into
+        // the stage read one tile ago, then the same waits and barriers as
+        // the compute waves (which no longer wait on transfers of their own)
+        int st = 0;
+        for (int64_t kt = 0; kt < KT; ++kt) {
+          prep_tile(kt + D, st == 0 ? NS - 1 : st - 1);
+          [&]<int... k>(std::integer_sequence<int, k...>) {
+            (issue_k(std::integral_constant<int, k>{}), ...);
+          }(std::make_integer_sequence<int, DPW>{});
+          if (kt + 1 < KT) {
+            const int64_t rest = KT - 2 - kt;
+            wait_tiles<DPW, D - 1>(rest < D - 1 ? (int)rest : D - 1);
+            raw_barrier();
+          }
+          st = st + 1 == NS ? 0 : st + 1;
+        }
+      } else {
+        compute_loop();
+      }
+    } else {
+      compute_loop();
     }
     // every wave has finished its LDS reads before the stages are reused
     wait_vm_lgkm0<0>();
     raw_barrier();
   }
 
-  if constexpr (KS > 1) {
-    using AE = std::remove_reference_t<decltype(acc[0][0][0])>;
+  // K-split tiles: the KS partial sums of each output are added through LDS.
+  // Two-way splits whose partial tiles fit in the ring's LDS at once: each
+  // wave of a pair keeps half of its blocks (kh 0 the first FM / 2 block
+  // rows, kh 1 the rest), hands the other half to its partner and stores
+  // only its own half (one exchange; every output is kh 0's sum plus kh 1's,
+  // added in either order with the same result). Otherwise one wave column
+  // at a time into the kh = 0 waves.
+  using AEt = std::remove_reference_t<decltype(acc[0][0][0])>;
+  constexpr bool HALVES = KS == 2 && FM % 2 == 0 &&
+                          S::WM * S::WN * FM * FN * NR * 64 * (int)sizeof(AEt) <=
+                              lds_bytes_dma<P, S, TA, TB>();
+  auto owned = [&](int i) { return !HALVES || ((i < FM / 2) == (kh == 0)); };
+  if constexpr (HALVES) {
+    AEt *red = reinterpret_cast<AEt *>(smem);
+    if (kh < KS) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        if (!owned(i))
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+              red[(((wpos * FM + i) * FN + j) * NR + q) * 64 + lane] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (kh < KS) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        if (owned(i))
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+              acc[i][j][q] += red[(((wpos * FM + i) * FN + j) * NR + q) * 64 + lane];
+    }
+    // the exchange is read before a persistent caller's next tile refills LDS
+    __syncthreads();
+    if (kh >= KS) return;   // loader waves
+  } else if constexpr (KS > 1) {
+    using AE = AEt;
     AE *red = reinterpret_cast<AE *>(smem);
 #pragma unroll 1
     for (int col = 0; col < S::WN; ++col) {
@@ -675,12 +746,15 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
       }
     }
     if (kh != 0) return;
+  } else if constexpr (SPEC) {
+    if (is_ld) return;
   }
 
   constexpr int GRP = T::GRP, LGN = GM::LGN;
   Out *C = reinterpret_cast<Out *>(g.C);
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
+    if (!owned(i)) continue;
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int64_t col = n0 + wn * S::WTN + (j / ILB) * MB * ILB + ILB * lr + j % ILB;

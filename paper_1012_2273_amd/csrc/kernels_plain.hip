@@ -126,9 +126,19 @@ template <int P, class S, bool TA, bool TB, class F> static int by_width(int vw,
 }
 
 template <int P, class S, class F> static int by_layout(int layout, int vw, F &f) {
-  if constexpr (P == PREC_BF16 && S::KS > 1) {
+  if constexpr (S::LDW > 0 && (P == PREC_SPLIT || P == PREC_SPLIT3)) {
+    // shapes with loader waves exist on the direct-to-LDS path only
+    if (layout != LAYOUT_NT || vw != 16) return -1;
+    if constexpr (dma_ok<P, S, false, true>()) return f(KTag<P, S, false, true, 16>{});
+    return -1;
+  } else if constexpr (S::LDW > 0 && (P == PREC_FSPLIT || P == PREC_FSPLIT3)) {
+    if (layout != LAYOUT_NN || vw != 16) return -1;
+    if constexpr (dma_ok<P, S, false, false>()) return f(KTag<P, S, false, false, 16>{});
+    return -1;
+  } else if constexpr ((P == PREC_BF16 && S::KS > 1) || S::LDW > 0) {
     // 16-bit K-split tiles exist on the direct-to-LDS path only (64-deep
-    // K-tiles; the register path's 32-deep tiles do not split)
+    // K-tiles; the register path's 32-deep tiles do not split), and so do
+    // the shapes with loader waves
     if (vw != 16) return -1;
     switch (layout) {
       case LAYOUT_NN:
@@ -178,6 +188,13 @@ using S64x64k2 = Shape<64, 64, 2, 2, 2>;
 using S32x32k2 = Shape<32, 32, 2, 2, 2>;
 using S64x64k4 = Shape<64, 64, 2, 2, 4, 32>;   // 1024 threads
 using S128x256w8 = Shape<128, 256, 2, 4, 1, 32>;
+#ifndef G355_LDW
+#define G355_LDW 4
+#endif
+#ifndef G355_LD_SHAPE
+#define G355_LD_SHAPE 128, 128, 2, 2, 2, 0, G355_LDW
+#endif
+using S128x128k2ld = Shape<G355_LD_SHAPE>;   // + loader waves
 
 template <int P, class F> static int by_cfg(int layout, int cfg, int vw, F &f) {
   switch (cfg) {
@@ -195,6 +212,7 @@ template <int P, class F> static int by_cfg(int layout, int cfg, int vw, F &f) {
         return by_layout<P, S64x64k4>(layout, vw, f);
       else
         return -1;   // binary64 only (the host never picks it)
+    case CFG_128x128_K2_LD: return by_layout<P, S128x128k2ld>(layout, vw, f);
     case CFG_128x256_W8:
       if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3 || P == PREC_FSPLIT ||
                     P == PREC_FSPLIT3)
