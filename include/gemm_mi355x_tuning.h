@@ -31,6 +31,19 @@ int gemm_tuning_force_tile_config(int id);
  */
 int gemm_tuning_force_ksplit_parts(int parts);
 
+/*
+ * gemm_tuning_force_split_form -- make this thread's gemm_split and
+ * gemm_split3 calls use one form: 0 the split step into the workspace and
+ * then the plane product, 1 one launch that splits each fragment in the
+ * registers of the waves that multiply it, 2 one launch whose loader waves
+ * split every tile once into LDS planes; -1 restores the size-based choice.
+ * Forms 1 and 2 need A and B rows of whole 16-byte vectors (binary32: 16-
+ * byte aligned, k and n multiples of 4) and fall back to form 0 otherwise.
+ * All forms give the same result bit for bit for the same tile shape.
+ * Errors: EINVAL (form below -1 or above 2).
+ */
+int gemm_tuning_force_split_form(int form);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ __all__ = [
     "gemm_backward", "gemm_grouped", "GroupedPlan", "GemmFn", "matmul", "load",
     "GemmError", "GemmArgError", "GEMM_F64", "GEMM_F32", "GEMM_BF16",
     "tile_configs", "force_tile_config", "gemm_plain_ksplit", "gemm_plain_ksplit_workspace_size",
-    "force_ksplit",
+    "force_ksplit", "force_split_form",
 ]
 
 
@@ -178,6 +178,15 @@ def gemm_plain_ksplit_noalloc(A, B, C):
     _lib.check(lib.gemm_plain_ksplit_noalloc(code, m, n, k, pa, lda, pb, ldb, pc, ldc,
                                              _stream(A)), "gemm_plain_ksplit_noalloc")
     return C
+
+
+def force_split_form(form: int):
+    """Make this thread's gemm_split / gemm_split3 calls use one form: 0 split
+    step and plane product, 1 one launch splitting fragments in registers, 2
+    one launch whose loader waves split tiles into LDS (-1: automatic). A
+    tuning knob for tests and tools; every form gives the same bits."""
+    _lib.check(_lib.load().gemm_tuning_force_split_form(int(form)),
+               "gemm_tuning_force_split_form")
 
 
 def force_ksplit(parts: int):

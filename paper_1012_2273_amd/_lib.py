@@ -31,7 +31,8 @@ EXPORTS = (
 # (GEMM_NOALLOC_SCRATCH_BYTES in the header)
 NOALLOC_SCRATCH_BYTES = 64 << 20
 # the tuning knobs of include/gemm_mi355x_tuning.h (tests and tuning tools)
-TUNING_EXPORTS = ("gemm_tuning_force_tile_config", "gemm_tuning_force_ksplit_parts")
+TUNING_EXPORTS = ("gemm_tuning_force_tile_config", "gemm_tuning_force_ksplit_parts",
+                  "gemm_tuning_force_split_form")
 
 
 class GemmProblem(ctypes.Structure):
@@ -65,6 +66,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
             "gemm_plain_ksplit": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
             "gemm_plain_ksplit_noalloc": (ci, [ci, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp]),
             "gemm_tuning_force_ksplit_parts": (ci, [ci]),
+            "gemm_tuning_force_split_form": (ci, [ci]),
             "gemm_split_convert": (ci, [i64, i64, vp, i64, ci, vp, vp, i64, vp]),
             "gemm_split": (ci, [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]),
             "gemm_split3_workspace_size": (sz, [i64, i64, i64]),

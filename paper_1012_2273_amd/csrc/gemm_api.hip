@@ -42,6 +42,9 @@ const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 // tuning tool that forces a shape never changes another thread's launches.
 static thread_local int t_force_cfg = -1;
 static thread_local int t_force_parts = -1;
+// Forms of the split products (split_form below); -1 lets the sizes decide.
+enum SplitForm : int { FORM_TWO_STEP = 0, FORM_REGISTERS = 1, FORM_LOADERS = 2 };
+static thread_local int t_force_form = -1;
 
 // The K-split shapes divide a 16-deep K-tile between two waves; the 16-bit
 // paths take 32-deep K-tiles of 8-element MFMA steps and do not offer them.
@@ -466,6 +469,13 @@ static int plain_prec(int dtype) {
   return dtype == GEMM_F64 ? PREC_F64 : dtype == GEMM_F32 ? PREC_F32 : PREC_BF16;
 }
 
+int gemm_tuning_force_split_form(int form) {
+  clear_error();
+  if (form < -1 || form > FORM_LOADERS) return set_error(GEMM_EINVAL, "split form out of range");
+  t_force_form = form;
+  return GEMM_OK;
+}
+
 int gemm_tuning_force_ksplit_parts(int parts) {
   clear_error();
   if (parts < -1 || parts == 0 || parts > 65535)
@@ -616,11 +626,38 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 // leave most CUs idle and have a short K loop (N <= 1000: 1.2-1.6x faster;
 // N = 1500: 7% slower, N = 2000: 18% slower, both precisions). It needs
 // operands fit for 16-byte direct-to-LDS transfers.
+//
+// The loader form (one launch as well): loader waves split binary32 tiles
+// once per workgroup into the LDS planes the compute waves read, so neither
+// the planes' pass through device memory nor the per-wave repetition remain.
+// It runs on the 128 x 128 loader-wave tile, one workgroup per CU. Measured
+// (us, two-step against loader form): three-way split N = 1500 77.8 / 62.5,
+// 2000 112.1 / 97.4, 2048 119.8 / 99.2, 2500 253.7 / 210.1, 3000 425.1 /
+// 376.6, 4096 671.6 / 726.3; two-way split N = 1200 31.0 / 39.2, 2000 67.0 /
+// 70.8, 2500 145.6 / 157.0, 4096 455.8 / 448.3 (the loaders' register loads
+// of binary32 tiles keep pace with six products per tile, not with three).
+// So the three-way split takes it from half a tile per CU to three tiles
+// per CU, the two-way split keeps the two steps.
+
+static int split_form(int np, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                      const void *B, int64_t ldb) {
+  const bool vec = vec_ok(A, lda, 4, k) && vec_ok(B, ldb, 4, n);
+  const int lprec = np == 2 ? PREC_LSPLIT : PREC_LSPLIT3;
+  const bool loaders = vec && plain_offered(lprec, LAYOUT_NN, CFG_128x128_K2_LD, 16);
+  const int f = t_force_form;
+  if (f == FORM_TWO_STEP) return FORM_TWO_STEP;
+  if (f == FORM_REGISTERS) return vec ? FORM_REGISTERS : FORM_TWO_STEP;
+  if (f == FORM_LOADERS) return loaders ? FORM_LOADERS : FORM_TWO_STEP;
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  const int64_t cus = device_cus();
+  if (vec && k <= 1024 && 2 * t128 <= cus) return FORM_REGISTERS;
+  if (np == 3 && loaders && 2 * t128 >= cus && t128 < 3 * cus) return FORM_LOADERS;
+  return FORM_TWO_STEP;
+}
+
 static bool split_one_launch(int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
                              const void *B, int64_t ldb) {
-  if (!vec_ok(A, lda, 4, k) || !vec_ok(B, ldb, 4, n) || k > 1024) return false;
-  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
-  return 2 * t128 <= (int64_t)device_cus();
+  return split_form(2, m, n, k, A, lda, B, ldb) == FORM_REGISTERS;
 }
 
 static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
@@ -644,11 +681,21 @@ static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A
   if ((uintptr_t)workspace % 16 != 0)
     return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  // Small products: one launch that splits each fragment in registers
-  // (the same result bit for bit, no planes).
-  if (split_one_launch(m, n, k, A, lda, B, ldb)) {
+  // Small products: one launch that splits each fragment in registers;
+  // one tile per CU: one launch whose loader waves split the tiles (both the
+  // same result bit for bit as the two steps, no planes in device memory).
+  const int form = split_form(np, m, n, k, A, lda, B, ldb);
+  if (form == FORM_REGISTERS) {
     GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
     return run_product(np == 2 ? PREC_FSPLIT : PREC_FSPLIT3, LAYOUT_NN, a, 4, s);
+  }
+  if (form == FORM_LOADERS) {
+    if ((rc = check_ld_range("A", lda, 4)) || (rc = check_ld_range("B", ldb, 4))) return rc;
+    GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
+    hipError_t e = launch_plain(np == 2 ? PREC_LSPLIT : PREC_LSPLIT3, LAYOUT_NN,
+                                CFG_128x128_K2_LD, 16, a, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return GEMM_OK;
   }
   char *ws = (char *)workspace;
   uint16_t *ap[3] = {nullptr, nullptr, nullptr}, *bp[3] = {nullptr, nullptr, nullptr};

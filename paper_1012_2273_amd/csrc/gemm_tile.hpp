@@ -42,7 +42,8 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 enum Prec : int {
   PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_SPLIT = 3, PREC_SPLIT3 = 4,
-  PREC_FSPLIT = 5, PREC_FSPLIT3 = 6   // split in registers from binary32 tiles
+  PREC_FSPLIT = 5, PREC_FSPLIT3 = 6,  // split in registers from binary32 tiles
+  PREC_LSPLIT = 7, PREC_LSPLIT3 = 8   // split by loader waves from binary32 into LDS planes
 };
 
 // Per-precision description of the MFMA used and the element types.
@@ -95,6 +96,25 @@ template <> struct Traits<PREC_FSPLIT3> {
   using E = float; using Op = u16x8; using Acc = f32x4; using Out = float;
   static constexpr int KPL = 8, BK = 32, PLANES = 1, GRP = 4, CVT = 3;
 };
+
+// The same products once more with the planes made inside the workgroup:
+// loader waves read binary32 tiles of A and B into registers, split them and
+// write the bfloat16 planes into the LDS ring, where the compute waves read
+// them exactly as the plane products read transferred planes (A K-contiguous,
+// B N-contiguous): the same bits again, without the planes in device memory.
+template <> struct Traits<PREC_LSPLIT> {
+  using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = G355_SPLIT_BK, PLANES = 2, GRP = 4, CVT = 0;
+};
+template <> struct Traits<PREC_LSPLIT3> {
+  using E = uint16_t; using Op = u16x8; using Acc = f32x4; using Out = float;
+  static constexpr int KPL = 8, BK = 32, PLANES = 3, GRP = 4, CVT = 0;
+};
+// Planes the loader waves make from binary32 operands (0: operands arrive
+// as they are used).
+template <int P> __host__ __device__ constexpr int lcv_of() {
+  return P == PREC_LSPLIT ? 2 : P == PREC_LSPLIT3 ? 3 : 0;
+}
 
 // x split into NP bfloat16 terms, each rounded to nearest even from what the
 // earlier terms leave (Dekker-style splitting): t0 = bf16(x), t1 = bf16(x -

@@ -624,12 +624,98 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
     mma_unit_s(std::integral_constant<int, PLU>{}, INB1{}, INB{}, std::integral_constant<int, -1>{});
   };
 
-  if (KT > 0) {
+  // Loader split (LCV planes): loader waves read the binary32 operands into
+  // registers, two K-tiles ahead in two register sets, split every element
+  // into LCV bfloat16 terms (split_pair, the rounding of the split step) and
+  // write each term into its plane of the LDS stage, at the places the
+  // plane transfers would fill. A chunk is one 16-byte LDS chunk of 8
+  // elements: 32 bytes of binary32, read as two 16-byte halves; a half
+  // outside the matrix reads as zeros (offset past the buffer record).
+  constexpr int LCV = lcv_of<P>();
+  static_assert(LCV == 0 || (SPEC && !TA && !TB && LCV == PL && KS == 2),
+                "the loader split runs on loader-wave shapes, NN operands");
+  constexpr int NCA = LCV ? OA::PERW : 0, NCB = LCV ? OB::PERW : 0, NCH = NCA + NCB;
+  // per chunk: the byte offset of its binary32 data in the tile (rows of A,
+  // K rows of B) and, packed, the K index the K edge is tested on (bits
+  // 0-15) and which halves lie inside the M/N extent (bits 16-17); the LDS
+  // place of chunk j is lds0 + j * 1 KiB * loader count
+  uint32_t lvoff[NCH > 0 ? NCH : 1], lkm[NCH > 0 ? NCH : 1];
+  const uint32_t lds0 = (uint32_t)(lwave * 1024 + lane * 16);
+  u32x4 lbuf[2][NCH > 0 ? NCH : 1][2];
+  auto lcv_setup = [&] {
+    if constexpr (LCV > 0) {
 #pragma unroll
-    for (int t = 0; t < D; ++t)
-      if (t < KT) issue_tile(t, t);
-    wait_tiles<DPW, D - 1>(KT < D ? (int)KT - 1 : D - 1);   // tile 0 has landed
-    raw_barrier();
+      for (int j = 0; j < NCA; ++j) {     // A: row r, K offset k (K-contiguous)
+        const int q = (lwave + j * OA::NW) * 64 + lane;
+        const int r = q / OA::CPR, c = q % OA::CPR;
+        const int k = (c ^ OA::swz(r)) * VE;
+        lvoff[j] = (uint32_t)((r * g.lda + k) * 4);
+        lkm[j] = (uint32_t)k | (m0 + r < g.M ? 3u << 16 : 0u);
+      }
+#pragma unroll
+      for (int j = 0; j < NCB; ++j) {     // B: K row r, column m (N-contiguous)
+        const int q = (lwave + j * OB::NW) * 64 + lane;
+        const int r = q / OB::CPR, c = q % OB::CPR;
+        const int mcol = (c ^ OB::swzm(r)) * VE;
+        lvoff[NCA + j] = (uint32_t)((r * g.ldb + mcol) * 4);
+        lkm[NCA + j] = (uint32_t)r | (n0 + mcol < g.N ? 1u << 16 : 0u) |
+                       (n0 + mcol + 4 < g.N ? 2u << 16 : 0u);
+      }
+    }
+  };
+  auto lcv_load = [&](auto set_tag, int64_t kt) {
+    constexpr int sx = decltype(set_tag)::value;
+    const int64_t k0 = kt * BK;
+    const int64_t rem = g.K - k0;
+    const int32_t krem = rem > 0x7fffffff ? 0x7fffffff : (int32_t)rem;
+    const __amdgpu_buffer_rsrc_t ra =
+        make_rsrc(reinterpret_cast<const float *>(g.A) + m0 * g.lda + k0);
+    const __amdgpu_buffer_rsrc_t rb =
+        make_rsrc(reinterpret_cast<const float *>(g.B) + k0 * g.ldb + n0);
+#pragma unroll
+    for (int j = 0; j < NCH; ++j)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int32_t kidx = (int32_t)(lkm[j] & 0xffffu) + (j < NCA ? 4 * h : 0);
+        const bool ok = ((lkm[j] >> (16 + h)) & 1u) && kidx < krem;
+        lbuf[sx][j][h] = raw_load<16>(j < NCA ? ra : rb, ok ? lvoff[j] + 16u * h : kOob);
+      }
+  };
+  auto lcv_store = [&](auto set_tag, int st) {
+    constexpr int sx = decltype(set_tag)::value;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) {
+      u32x4 o[LCV > 0 ? LCV : 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // elements taken out of the vector by value first: a bit cast of a
+        // vector element in place read element 0 whatever the index
+        const uint32_t u0 = lbuf[sx][j][e / 2][(e % 2) * 2];
+        const uint32_t u1 = lbuf[sx][j][e / 2][(e % 2) * 2 + 1];
+        uint32_t t[LCV > 0 ? LCV : 1];
+        split_pair<(LCV > 0 ? LCV : 1)>(__builtin_bit_cast(float, u0),
+                                        __builtin_bit_cast(float, u1), t);
+#pragma unroll
+        for (int p = 0; p < LCV; ++p) o[p][e] = t[p];
+      }
+#pragma unroll
+      for (int p = 0; p < LCV; ++p) {
+        const int slot = j < NCA ? j * OA::NW : (j - NCA) * OB::NW;
+        char *dst = (j < NCA ? regA(st, p) : regB(st, p)) + lds0 + slot * 1024;
+        *reinterpret_cast<u32x4 *>(dst) = o[p];
+      }
+    }
+  };
+
+  if (KT > 0) {
+    if constexpr (LCV == 0) {
+#pragma unroll
+      for (int t = 0; t < D; ++t)
+        if (t < KT) issue_tile(t, t);
+      wait_tiles<DPW, D - 1>(KT < D ? (int)KT - 1 : D - 1);   // tile 0 has landed
+    }
+    static_assert(LCV == 0 || NS == 2, "loader split: two LDS stages");
+    if constexpr (LCV == 0) raw_barrier();
     auto compute_loop = [&] {
       read_unit(0, 0, I0{});
       int st = 0;
@@ -649,7 +735,45 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
         }
       }
     };
-    if constexpr (SPEC) {
+    if constexpr (LCV > 0) {
+      // every use of the loaders' registers sits in this branch (the first
+      // barrier too, duplicated in the compute branch), so that they share
+      // no live range with the compute waves' registers
+      if (is_ld) {
+        lcv_setup();
+        using I1 = std::integral_constant<int, 1>;
+        // Loads of tiles past the end are issued too (every offset then lies
+        // past the buffer record: zeros, no memory access), so that every
+        // path carries the same loads in the same order and the compiler's
+        // waits retire exactly the older register set, never the newer one.
+        lcv_load(I0{}, 0);
+        lcv_load(I1{}, 1);
+        lcv_store(I0{}, 0);
+        lcv_load(I0{}, 2);
+        wait_vm_lgkm0<63>();     // the planes of tile 0 are written
+        raw_barrier();
+        // tile t is split into stage t % 2 from register set t % 2 once the
+        // compute waves have passed the barrier that ends tile t - 2; then the
+        // set takes tile t + 2
+        for (int64_t kt = 0; kt < KT; kt += 2) {
+          if (kt + 1 < KT) {
+            lcv_store(I1{}, 1);
+            lcv_load(I1{}, kt + 3);
+            wait_vm_lgkm0<63>();
+            raw_barrier();
+          }
+          if (kt + 2 < KT) {
+            lcv_store(I0{}, 0);
+            lcv_load(I0{}, kt + 4);
+            wait_vm_lgkm0<63>();
+            raw_barrier();
+          }
+        }
+      } else {
+        raw_barrier();
+        compute_loop();
+      }
+    } else if constexpr (SPEC) {
       if (is_ld) {
         // loader waves: per K-tile, the transfers of the tile D ahead into
         // the stage read one tile ago, then the same waits and barriers as

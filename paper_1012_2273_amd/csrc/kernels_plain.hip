@@ -126,7 +126,17 @@ template <int P, class S, bool TA, bool TB, class F> static int by_width(int vw,
 }
 
 template <int P, class S, class F> static int by_layout(int layout, int vw, F &f) {
-  if constexpr (S::LDW > 0 && (P == PREC_SPLIT || P == PREC_SPLIT3)) {
+  if constexpr (P == PREC_LSPLIT || P == PREC_LSPLIT3) {
+    // binary32 operands as given (NN, 16-byte rows), split by the loader
+    // waves: shapes with loader waves only
+    if constexpr (S::LDW == 0 || S::KS != 2) {
+      return -1;
+    } else {
+      if (layout != LAYOUT_NN || vw != 16) return -1;
+      if constexpr (dma_ok<P, S, false, false>()) return f(KTag<P, S, false, false, 16>{});
+      return -1;
+    }
+  } else if constexpr (S::LDW > 0 && (P == PREC_SPLIT || P == PREC_SPLIT3)) {
     // shapes with loader waves exist on the direct-to-LDS path only
     if (layout != LAYOUT_NT || vw != 16) return -1;
     if constexpr (dma_ok<P, S, false, true>()) return f(KTag<P, S, false, true, 16>{});
@@ -215,7 +225,7 @@ template <int P, class F> static int by_cfg(int layout, int cfg, int vw, F &f) {
     case CFG_128x128_K2_LD: return by_layout<P, S128x128k2ld>(layout, vw, f);
     case CFG_128x256_W8:
       if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_SPLIT3 || P == PREC_FSPLIT ||
-                    P == PREC_FSPLIT3)
+                    P == PREC_FSPLIT3 || P == PREC_LSPLIT || P == PREC_LSPLIT3)
         return by_layout<P, S128x256w8>(layout, vw, f);
       else
         return -1;   // bfloat16-MFMA products only (the host never picks it)
@@ -232,6 +242,8 @@ template <class F> static int visit(int prec, int layout, int cfg, int vw, F &f)
     case PREC_SPLIT3: return by_cfg<PREC_SPLIT3>(layout, cfg, vw, f);
     case PREC_FSPLIT: return by_cfg<PREC_FSPLIT>(layout, cfg, vw, f);
     case PREC_FSPLIT3: return by_cfg<PREC_FSPLIT3>(layout, cfg, vw, f);
+    case PREC_LSPLIT: return by_cfg<PREC_LSPLIT>(layout, cfg, vw, f);
+    case PREC_LSPLIT3: return by_cfg<PREC_LSPLIT3>(layout, cfg, vw, f);
   }
   return -1;
 }

@@ -34,7 +34,11 @@ SHAPES = [(2000, 2000, 2000), (1000, 37, 1003), (130, 257, 61), (65, 9, 1)]
 def G(gpu_device):
     import paper_1012_2273_amd as G
     G.load()
-    return G
+    # the split step writes the planes only in the two-step form (larger
+    # products otherwise split inside the product launch)
+    G.force_split_form(0)
+    yield G
+    G.force_split_form(-1)
 
 
 def _torch():
