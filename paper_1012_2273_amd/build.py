@@ -51,36 +51,50 @@ def _stale(target, deps):
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def _compile(src, force):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(src, force, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
     if force or _stale(obj, [src, *_headers(), os.path.abspath(__file__)]):
-        cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *CFLAGS, *extra, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(force: bool = False, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the CPU checks
+# of the ABI's validation paths (the device code is built as usual).
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build(force: bool = False, jobs: int | None = None, sanitize: bool = False,
+          out: str | None = None) -> str:
+    """Compile every unit under csrc/ and link the library. ``sanitize`` adds
+    the host sanitizers (objects under _build/san/, library at ``out``)."""
+    build_dir = os.path.join(BUILD, "san") if sanitize else BUILD
+    lib = out or (os.path.join(build_dir, "libgemm_mi355x_san.so") if sanitize else LIB)
+    os.makedirs(build_dir, exist_ok=True)
     srcs = _sources()
     jobs = jobs or min(8, os.cpu_count() or 1)
+    extra = SAN_FLAGS if sanitize else []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, force), srcs))
-    if force or _stale(LIB, objs):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda s: _compile(s, force, build_dir, extra), srcs))
+    if force or _stale(lib, objs):
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *extra]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed:\n{r.stderr}")
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--force", action="store_true")
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--sanitize", action="store_true",
+                    help="host AddressSanitizer/UBSan build under _build/san/ (CPU checks)")
     a = ap.parse_args()
-    print(build(a.force, a.j))
+    print(build(a.force, a.j, sanitize=a.sanitize))
     sys.exit(0)
