@@ -117,12 +117,15 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
       if (t128 > cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x64_K2;
       return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
+    // 16-bit: the 128 x 128 tile with loader waves holds a CU by itself (its
+    // ring takes 128 KiB of LDS), so it runs where one round covers every
+    // tile; from there to two tiles per CU the 8-wave tile, three of whose
+    // workgroups share a CU (bf16 N = 2500: 154 us with the loader tile in
+    // two rounds)
     case PREC_BF16:
-      if (t128 >= 2 * cus) return CFG_128x256_W8;
-      if (t128 >= big) return CFG_128x128_K2_LD;
-      return t128 >= mid ? CFG_64x64 : CFG_32x32;
     case PREC_SPLIT:
       if (t128 >= 2 * cus) return CFG_128x256_W8;
+      if (t128 > cus) return CFG_128x128_W8;
       if (t128 >= big) return CFG_128x128_K2_LD;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     default:  // three planes, fused splits

@@ -201,3 +201,43 @@ def test_grouped_integer_bit_exact(G):
     for (A, B), C in zip(probs, Cs):
         assert np.array_equal(C.cpu().double().numpy(), oracle.gemm(A, B))
     plan.close()
+
+
+@pytest.mark.parametrize("tname", ["f64", "f32"])
+def test_grouped_unaligned_rows_every_edge(G, tname):
+    """Problems whose rows are not whole 16-byte vectors (odd binary64
+    sizes, binary32 sizes not multiples of 4) run in the persistent kernel's
+    register path: ragged M, N and K edges, single rows and columns, K
+    shorter than a K-tile; each against the oracle, and integer entries bit
+    for bit."""
+    torch = _torch()
+    dt = np.float64 if tname == "f64" else np.float32
+    tol = 1e-12 if tname == "f64" else 1e-5
+    shapes = [(33, 65, 17), (129, 1, 3), (1, 127, 255), (257, 255, 129), (131, 67, 1001),
+              (67, 133, 5), (255, 257, 258), (9, 7, 1)]
+    As, Bs, host = [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A, B = inputs.uniform_mnk(m, n, k, 880 + i, dtype=dt)
+        host.append((A, B))
+        As.append(dev(A, torch))
+        Bs.append(dev(B, torch))
+    plan = G.GroupedPlan(As, Bs)
+    Cs = plan.run()
+    torch.cuda.synchronize()
+    for (A, B), C in zip(host, Cs):
+        assert oracle.relerr_fro(C.cpu().double().numpy(), oracle.gemm(A, B)) <= tol
+    plan.close()
+    # integer entries: exact
+    As, Bs, host = [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A = inputs.integers((m, k), 890 + i, dt, 1)[0]
+        B = inputs.integers((k, n), 990 + i, dt, 1)[0]
+        host.append((A, B))
+        As.append(dev(A, torch))
+        Bs.append(dev(B, torch))
+    plan = G.GroupedPlan(As, Bs)
+    Cs = plan.run()
+    torch.cuda.synchronize()
+    for (A, B), C in zip(host, Cs):
+        assert np.array_equal(C.cpu().double().numpy(), oracle.gemm(A, B))
+    plan.close()
