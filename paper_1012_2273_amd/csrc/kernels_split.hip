@@ -132,16 +132,23 @@ split_pair_kernel(SplitJob<NP> a, SplitJob<NP> b, int64_t na) {
   if ((int64_t)blockIdx.x < na) {
     // A: plane[r][c] for c < pad (zeros past cols)
     const int64_t r0 = (int64_t)(blockIdx.x / a.tiles_c) * T, c0 = (int64_t)(blockIdx.x % a.tiles_c) * T;
+    // all four loads first, so that four are in flight per lane (one at a
+    // time left the kernel waiting on memory latency)
+    float v[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + 256 * i;
+      const int64_t r = r0 + idx / 16, c = c0 + (idx % 16) * 4;
+      load4<VEC>(a.X, a.ldx, a.rows, a.cols, r, c, v[i]);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + 256 * i;
       const int64_t r = r0 + idx / 16, c = c0 + (idx % 16) * 4;
       if (r >= a.rows || c >= a.pad) continue;
-      float v[4];
-      load4<VEC>(a.X, a.ldx, a.rows, a.cols, r, c, v);
       uint16_t s[4][NP];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) split_x<NP>(v[e], s[e]);
+      for (int e = 0; e < 4; ++e) split_x<NP>(v[i][e], s[e]);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         uint16_t *d = a.out.p[p] + r * a.ldo + c;
@@ -158,16 +165,20 @@ split_pair_kernel(SplitJob<NP> a, SplitJob<NP> b, int64_t na) {
   // B: input tile rows r0.. (K), cols c0.. (N); planes out[c][r], r < pad
   const int64_t bid = (int64_t)blockIdx.x - na;
   const int64_t r0 = (bid / b.tiles_c) * T, c0 = (bid % b.tiles_c) * T;
+  float v[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i;
+    load4<VEC>(b.X, b.ldx, b.rows, b.cols, r0 + idx / 16, c0 + (idx % 16) * 4, v[i]);
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int idx = tid + 256 * i;
     const int rr = idx / 16, cc = (idx % 16) * 4;
-    float v[4];
-    load4<VEC>(b.X, b.ldx, b.rows, b.cols, r0 + rr, c0 + cc, v);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       uint16_t s[NP];
-      split_x<NP>(v[e], s);
+      split_x<NP>(v[i][e], s);
 #pragma unroll
       for (int p = 0; p < NP; ++p) sh[p][rr][cc + e] = s[p];
     }
