@@ -32,7 +32,8 @@ Outside the timed step loop (each skippable):
   sweep     binary64 at the paper's sizes N = 10 ... 2000 plus 4096: median
             per-call rate (2N^3 and the paper's N^2(2N-1) count), error; for
             N <= 100 also single-call latency and 1000 back-to-back launches;
-            and six rectangular binary64 shapes (m x k times k x n)
+            and six rectangular binary64 shapes (m x k times k x n); the K
+            split in binary32 and with bfloat16 inputs on two deep-K shapes
   transfer  N = 2000 binary64 with the operands on the host (pinned): H2D of
             A and B, the product, D2H of C, timed together (never ``value``)
   host      the host CPU (model, sockets, cores, threads), the single-thread
@@ -265,6 +266,42 @@ def rect_sweep(G, torch, dev, stream, inputs, ref):
             del ws
         out[f"{m}x{n}x{k}"] = d
         del Ad, Bd, Cd
+    return out
+
+
+KSPLIT_32_16 = [(1024, 1024, 8192), (256, 256, 65536)]
+
+
+def ksplit_sweep(G, torch, dev, stream, inputs, ref):
+    """gemm_plain against gemm_plain_ksplit in binary32 and with bfloat16
+    inputs on deep-K shapes; bf16 errors against the oracle of the rounded
+    inputs (``rel_err``) and of the binary32 data (``rel_err_path``)."""
+    out = {}
+    for m, n, k in KSPLIT_32_16:
+        print(f"sweep: K split {m}x{n}x{k} binary32 and bf16", file=sys.stderr, flush=True)
+        A, B = inputs.uniform_mnk(m, n, k, 6_000_000 + m + n + k, dtype=np.float32)
+        A32d, B32d = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        for name, Ad, Bd in (("f32", A32d, B32d),
+                             ("bf16", A32d.to(torch.bfloat16), B32d.to(torch.bfloat16))):
+            Cd = torch.empty((m, n), dtype=torch.float32, device=dev)
+            fl = 2.0 * m * n * k
+            tp = _median_call_ms(lambda: G.gemm_plain(Ad, Bd, Cd), torch, stream) * 1e-3
+            need = G.gemm_plain_ksplit_workspace_size(
+                G.GEMM_F32 if name == "f32" else G.GEMM_BF16, m, n, k)
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+            tk = _median_call_ms(lambda: G.gemm_plain_ksplit(Ad, Bd, Cd, ws), torch, stream) * 1e-3
+            d = {"plain_gflops": round(fl / tp / 1e9, 2), "ksplit_ms": round(tk * 1e3, 5),
+                 "ksplit_gflops": round(fl / tk / 1e9, 2), "workspace_bytes": need}
+            if ref is not None:
+                C = Cd.cpu().double().numpy()
+                if name == "bf16":
+                    Ar, Br = Ad.double().cpu().numpy(), Bd.double().cpu().numpy()
+                    d["rel_err"] = float(f"{ref.err(C, Ar, Br, seed=m + k):.3e}")
+                    d["rel_err_path"] = float(f"{ref.err(C, A, B, seed=m + k):.3e}")
+                else:
+                    d["rel_err"] = float(f"{ref.err(C, A, B, seed=m + k):.3e}")
+            out[f"{name}_{m}x{n}x{k}"] = d
+            del ws, Cd
     return out
 
 
@@ -610,10 +647,11 @@ def main():
             errs[gpath] = worst
 
     # ------------------------------------------- outside the timed step loop
-    sweep = rect = None
+    sweep = rect = ksw = None
     if not args.no_sweep:
         sweep = fp64_sweep(G, torch, dev, stream, inputs, ref, full={N: ref64})
         rect = rect_sweep(G, torch, dev, stream, inputs, ref)
+        ksw = ksplit_sweep(G, torch, dev, stream, inputs, ref)
     xfer = None
     if not args.no_transfer:
         A, B = host["fp64"]
@@ -673,6 +711,7 @@ def main():
         "cpu_baseline": cpu,
         "sweep_fp64": sweep,
         "sweep_rect_fp64": rect,
+        "sweep_ksplit_f32_bf16": ksw,
         "transfer_inclusive": xfer,
         "host": hinfo,
     }
