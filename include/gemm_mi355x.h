@@ -272,7 +272,8 @@ typedef struct gemm_plan gemm_plan;
 /* Plan flags. */
 enum {
     GEMM_PLAN_AUTOTUNE = 1,   /* time candidate tile policies on the device now */
-    GEMM_PLAN_NO_GRAPH = 2    /* launch directly instead of through a hipGraph  */
+    GEMM_PLAN_NO_GRAPH = 2,   /* launch directly instead of through a hipGraph  */
+    GEMM_PLAN_NO_PACK = 4     /* read every operand where it is (no copies)     */
 };
 
 /*
@@ -289,6 +290,17 @@ enum {
  *              synchronises it before returning.
  * The plan owns its device descriptor and queue arrays and its hipGraphExec
  * until gemm_grouped_plan_destroy. Tuning overwrites the C matrices.
+ * Packing (unless GEMM_PLAN_NO_PACK): a problem (m, n, k > 0) whose A or B
+ * rows are not whole 16-byte vectors (binary64 k or n odd, binary32 not
+ * multiples of 4, or a base or leading dimension off 16 bytes) gets
+ * plan-owned copies A' (m x k') and B' (k' x n'), k' and n' rounded up to
+ * whole vectors and zero padded, (m k' + k' n') * element size bytes of
+ * device memory in all; every run first copies A and B into them (one
+ * launch for every such problem), then computes C from the copies, which
+ * lets the persistent kernel use 16-byte transfers for every problem. C is
+ * written in place as always. A packed problem's C equals, bit for bit, a
+ * single gemm_plain launch at the same tile shape on A' and B' (its first n
+ * columns); with GEMM_PLAN_NO_PACK it equals one on A and B themselves.
  * Errors: EINVAL (count < 0, bad flags, negative sizes), ENULL, ELD,
  * EUNSUPPORTED, ENOMEM, EHIP.
  */
@@ -303,9 +315,10 @@ int gemm_grouped_run(gemm_plan *plan, void *stream);
 
 /* gemm_grouped_plan_update -- replace the A, B, C pointers (and nothing else)
  * of every problem; sizes and leading dimensions must equal the plan's.
- * A problem whose A and B were 16-byte aligned at plan creation runs in the
- * kernel that moves operands in 16-byte transfers: its new A and B must be
- * 16-byte aligned as well (other problems take any alignment). Takes effect
+ * A problem whose own A and B allowed 16-byte transfers at plan creation
+ * runs in the kernel that reads them that way: its new A and B must be
+ * 16-byte aligned as well (packed problems and, with GEMM_PLAN_NO_PACK, the
+ * other problems take any alignment). Takes effect
  * for the next run without re-capture; synchronous copy. Nothing changes
  * when the call fails.
  * Errors: ENULL, EINVAL (count or a size differs, or a 16-byte planned

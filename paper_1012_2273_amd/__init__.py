@@ -16,7 +16,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (GEMM_BF16, GEMM_F32, GEMM_F64, GEMM_PLAN_AUTOTUNE, GEMM_PLAN_NO_GRAPH,
-                   GemmArgError, GemmError)
+                   GEMM_PLAN_NO_PACK, GemmArgError, GemmError)
 
 __all__ = [
     "gemm_plain", "gemm_split", "gemm_split_convert", "gemm_split_workspace_size",
@@ -332,10 +332,13 @@ class GroupedPlan:
 
     ``autotune=True`` times candidate tile policies on the given data once
     (overwriting the C_i); ``tune_cache`` is a JSON path for the chosen policy.
+    ``pack=False`` reads every operand where it is instead of copying those
+    whose rows are not 16-byte vectors into padded plan-owned buffers.
     ``run()`` replays the captured hipGraph on torch's current stream.
     """
 
-    def __init__(self, As, Bs, Cs=None, autotune=False, tune_cache=None, graph=True):
+    def __init__(self, As, Bs, Cs=None, autotune=False, tune_cache=None, graph=True,
+                 pack=True):
         torch = _torch()
         if not (len(As) == len(Bs)):
             raise GemmArgError(_lib.GEMM_EINVAL, "GroupedPlan", "list lengths differ")
@@ -347,7 +350,8 @@ class GroupedPlan:
         self.As, self.Bs, self.Cs = list(As), list(Bs), list(Cs)
         self._arr = _problems(self.As, self.Bs, self.Cs)
         self.device = As[0].device if As else torch.device("cuda:0")
-        flags = (GEMM_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else GEMM_PLAN_NO_GRAPH)
+        flags = ((GEMM_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else GEMM_PLAN_NO_GRAPH)
+                 | (0 if pack else GEMM_PLAN_NO_PACK))
         lib = _lib.load()
         h = ctypes.c_void_p()
         stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)

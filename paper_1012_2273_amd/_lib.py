@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libgemm_mi355x.so")
 GEMM_OK, GEMM_EINVAL, GEMM_ENULL, GEMM_ELD, GEMM_EWORKSPACE = 0, 1, 2, 3, 4
 GEMM_EUNSUPPORTED, GEMM_EHIP, GEMM_ENOMEM, GEMM_ESTATE = 5, 6, 7, 8
 GEMM_F64, GEMM_F32, GEMM_BF16 = 0, 1, 2
-GEMM_PLAN_AUTOTUNE, GEMM_PLAN_NO_GRAPH = 1, 2
+GEMM_PLAN_AUTOTUNE, GEMM_PLAN_NO_GRAPH, GEMM_PLAN_NO_PACK = 1, 2, 4
 
 # every symbol the header declares; the CPU tests check they are exported
 EXPORTS = (

@@ -9,6 +9,14 @@
 // The tuner runs the persistent kernel on the caller's data for candidate
 // policies (one class at a time, largest class first, every tile config)
 // and keeps the fastest measured policy.
+//
+// Problems whose operands do not allow 16-byte transfers (binary64 rows of
+// odd length, binary32 rows not a multiple of 4, unaligned bases) are packed
+// unless the caller opts out: each run first copies their A and B into
+// plan-owned buffers with zero-padded, 16-byte rows (one launch for all of
+// them), and the persistent kernel reads those copies on the direct-to-LDS
+// path. The copy moves about as many bytes as the product reads and costs
+// less than the register path's element loads would.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,7 +68,16 @@ struct gemm_plan {
   uint32_t *d_counter = nullptr;
   int64_t items_cap = 0;
   int32_t n_items = 0;
-  int32_t n_vec = 0;          // items of problems with 16-byte operands (listed first)
+  int32_t n_group[g355::kQueues] = {0, 0, 0};   // items per queue (see internal.h), in that order
+  // packing: per problem the index of its A copy job (its B job follows), or -1
+  std::vector<int32_t> pack_job;
+  std::vector<g355::PackJob> jobs;
+  g355::PackJob *d_jobs = nullptr;
+  void *d_pack = nullptr;
+  int64_t pack_blocks = 0;
+  // the copies run on a side stream beside the first queue's kernel
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int grid = 0;
   int policy[g355::NCLASS];
   hipGraph_t graph = nullptr;
@@ -74,8 +91,15 @@ static int hip_fail(hipError_t e, const char *what) {
   return set_error(GEMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy, int32_t &n_vec) {
-  struct Keyed { int vec; int64_t cost; int64_t order; WorkItem w; };
+// Queue of a problem: 0 own operands with 16-byte rows, 1 packed, 2 register path.
+static int queue_of(const gemm_plan &p, size_t i) {
+  if (!p.pack_job.empty() && p.pack_job[i] >= 0) return 1;
+  return p.dprob_host[i].vec ? 0 : 2;
+}
+
+static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy,
+                                        int32_t (&n_group)[kQueues]) {
+  struct Keyed { int queue; int64_t cost; int64_t order; WorkItem w; };
   std::vector<Keyed> v;
   int64_t order = 0;
   for (size_t i = 0; i < p.probs.size(); ++i) {
@@ -85,28 +109,28 @@ static std::vector<WorkItem> plan_items(const gemm_plan &p, const int *policy, i
     const CfgInfo &ci = cfg_info(cfg);
     const int64_t tm = (q.m + ci.bm - 1) / ci.bm, tn = (q.n + ci.bn - 1) / ci.bn;
     const int64_t cost = (int64_t)ci.bm * ci.bn * std::max<int64_t>(q.k, 1);
+    const int queue = queue_of(p, i);
     for (int64_t a = 0; a < tm; ++a)
       for (int64_t b = 0; b < tn; ++b)
-        v.push_back({p.dprob_host[i].vec, cost, order++,
-                     WorkItem{(int32_t)i, cfg, (int32_t)a, (int32_t)b}});
+        v.push_back({queue, cost, order++, WorkItem{(int32_t)i, cfg, (int32_t)a, (int32_t)b}});
   }
-  // 16-byte problems first (their own kernel), each group largest work first
+  // queue by queue, each largest work first
   std::stable_sort(v.begin(), v.end(), [](const Keyed &x, const Keyed &y) {
-    if (x.vec != y.vec) return x.vec > y.vec;
+    if (x.queue != y.queue) return x.queue < y.queue;
     return x.cost > y.cost;
   });
   std::vector<WorkItem> out(v.size());
-  n_vec = 0;
+  for (int g = 0; g < kQueues; ++g) n_group[g] = 0;
   for (size_t i = 0; i < v.size(); ++i) {
     out[i] = v[i].w;
-    n_vec += v[i].vec ? 1 : 0;
+    n_group[v[i].queue]++;
   }
   return out;
 }
 
 static int upload_items(gemm_plan &p, const int *policy) {
-  int32_t n_vec = 0;
-  std::vector<WorkItem> items = plan_items(p, policy, n_vec);
+  int32_t n_group[kQueues];
+  std::vector<WorkItem> items = plan_items(p, policy, n_group);
   if ((int64_t)items.size() > 0x7fffffff) return set_error(GEMM_EINVAL, "too many tiles");
   if ((int64_t)items.size() > p.items_cap) return set_error(GEMM_ESTATE, "item capacity exceeded");
   if (!items.empty()) {
@@ -115,16 +139,32 @@ static int upload_items(gemm_plan &p, const int *policy) {
     if (e != hipSuccess) return hip_fail(e, "upload work items");
   }
   p.n_items = (int32_t)items.size();
-  p.n_vec = n_vec;
+  std::memcpy(p.n_group, n_group, sizeof(n_group));
   std::memcpy(p.policy, policy, sizeof(p.policy));
   return GEMM_OK;
 }
 
+// Counter reset, then the three queues' kernels in order on `s`; the
+// operand copies run on the side stream beside queue 0 and join `s` before
+// queue 1 reads them. Captured as is, the fork and join become graph edges.
 static int launch_direct(gemm_plan &p, hipStream_t s) {
   hipError_t e = launch_counter_reset(p.d_counter, s);
-  if (e == hipSuccess)
-    e = launch_grouped(p.prec, p.d_probs, p.d_items, p.n_vec, p.n_items - p.n_vec, p.d_counter,
-                       p.grid, s);
+  const bool pack = !p.jobs.empty() && p.n_group[1] > 0;
+  if (e == hipSuccess && pack) {
+    e = hipEventRecord(p.ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p.side, p.ev_fork, 0);
+    if (e == hipSuccess)
+      e = launch_pack(p.prec, p.d_jobs, (int32_t)p.jobs.size(), p.pack_blocks, p.side);
+    if (e == hipSuccess) e = hipEventRecord(p.ev_join, p.side);
+  }
+  const WorkItem *it = p.d_items;
+  for (int q = 0; q < kQueues && e == hipSuccess; ++q) {
+    if (q == 1 && pack) e = hipStreamWaitEvent(s, p.ev_join, 0);
+    if (e == hipSuccess)
+      e = launch_grouped(p.prec, q < 2, p.d_probs, it, p.n_group[q],
+                         p.d_counter + q * kCounterStride, p.grid, s);
+    it += p.n_group[q];
+  }
   if (e != hipSuccess) return hip_fail(e, "grouped launch");
   return GEMM_OK;
 }
@@ -271,6 +311,11 @@ static void plan_free(gemm_plan *p) {
   if (p->d_probs) hipFree(p->d_probs);
   if (p->d_items) hipFree(p->d_items);
   if (p->d_counter) hipFree(p->d_counter);
+  if (p->d_jobs) hipFree(p->d_jobs);
+  if (p->d_pack) hipFree(p->d_pack);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  if (p->ev_join) hipEventDestroy(p->ev_join);
+  if (p->side) hipStreamDestroy(p->side);
   delete p;
 }
 
@@ -316,6 +361,67 @@ static GroupedProblem to_device(const gemm_problem &q, size_t es) {
   return d;
 }
 
+// Lays out the packed copies of every problem whose operands do not allow
+// 16-byte transfers (and whose product reads them: m, n, k > 0) in one
+// device buffer and points those problems at them: A' = m x k' and B' =
+// k' x n' with k', n' rounded up to whole vectors, zero padded, each copy
+// 256-byte aligned. The problems then run with K = k' (the padding adds
+// zero products) in the kernel of 16-byte transfers.
+static int setup_packing(gemm_plan &p, size_t es) {
+  const int64_t v = 16 / (int64_t)es;
+  const size_t count = p.probs.size();
+  p.pack_job.assign(count, -1);
+  std::vector<std::pair<size_t, size_t>> off(count);
+  size_t total = 0;
+  auto take = [&](int64_t elems) {
+    const size_t at = total;
+    total += ((size_t)elems * es + 255) / 256 * 256;
+    return at;
+  };
+  for (size_t i = 0; i < count; ++i) {
+    const gemm_problem &q = p.probs[i];
+    if (q.m == 0 || q.n == 0 || q.k == 0 || p.dprob_host[i].vec) continue;
+    const int64_t kp = (q.k + v - 1) / v * v, np = (q.n + v - 1) / v * v;
+    if ((uint64_t)kp * es >= (1ull << 24) || (uint64_t)np * es >= (1ull << 24))
+      return set_error(GEMM_EINVAL, "packed row pitch too large (problem " + std::to_string(i) + ")");
+    off[i].first = take(q.m * kp);
+    off[i].second = take(kp * np);
+    p.pack_job[i] = (int32_t)p.jobs.size();
+    p.jobs.push_back(PackJob{q.A, nullptr, q.lda, kp, q.m, q.k, q.m, kp, 0});
+    p.jobs.push_back(PackJob{q.B, nullptr, q.ldb, np, q.k, q.n, kp, np, 0});
+  }
+  if (p.jobs.empty()) return GEMM_OK;
+  hipError_t e = hipMalloc(&p.d_pack, total);
+  if (e == hipSuccess) e = hipMalloc(&p.d_jobs, sizeof(PackJob) * p.jobs.size());
+  if (e != hipSuccess)
+    return set_error(GEMM_ENOMEM, std::string("packed operand copies: ") + hipGetErrorString(e));
+  e = hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p.ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(e, "copy stream");
+  char *base = static_cast<char *>(p.d_pack);
+  int64_t blocks = 0;
+  for (size_t i = 0; i < count; ++i) {
+    if (p.pack_job[i] < 0) continue;
+    PackJob &ja = p.jobs[p.pack_job[i]], &jb = p.jobs[p.pack_job[i] + 1];
+    ja.dst = base + off[i].first;
+    jb.dst = base + off[i].second;
+    GroupedProblem &d = p.dprob_host[i];
+    d.A = ja.dst; d.lda = ja.dld;
+    d.B = jb.dst; d.ldb = jb.dld;
+    d.K = ja.dcols;
+    d.vec = 1;
+  }
+  for (PackJob &j : p.jobs) {
+    j.first_block = blocks;
+    blocks += (j.drows + kPackRows - 1) / kPackRows;
+  }
+  p.pack_blocks = blocks;
+  e = hipMemcpy(p.d_jobs, p.jobs.data(), sizeof(PackJob) * p.jobs.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload copy jobs");
+  return GEMM_OK;
+}
+
 }  // namespace g355
 
 using namespace g355;
@@ -327,7 +433,7 @@ int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *pro
   clear_error();
   if (!out) return set_error(GEMM_ENULL, "out is NULL");
   *out = nullptr;
-  if (flags & ~(GEMM_PLAN_AUTOTUNE | GEMM_PLAN_NO_GRAPH))
+  if (flags & ~(GEMM_PLAN_AUTOTUNE | GEMM_PLAN_NO_GRAPH | GEMM_PLAN_NO_PACK))
     return set_error(GEMM_EINVAL, "unknown plan flags");
   int rc = validate_problems(dtype, probs, count);
   if (rc) return rc;
@@ -341,6 +447,7 @@ int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *pro
   p->probs.assign(probs, probs + count);
   const size_t es = dtype == GEMM_F64 ? 8 : 4;
   p->dprob_host.resize(count);
+  p->pack_job.assign(count, -1);
   int64_t cap = 0;
   for (int32_t i = 0; i < count; ++i) {
     p->dprob_host[i] = to_device(probs[i], es);
@@ -354,6 +461,7 @@ int gemm_grouped_plan_create(gemm_plan **out, int dtype, const gemm_problem *pro
     }
   }
   p->items_cap = cap;
+  if (!(flags & GEMM_PLAN_NO_PACK) && (rc = setup_packing(*p, es))) { plan_free(p); return rc; }
   hipError_t e = hipSuccess;
   if (count > 0) e = hipMalloc(&p->d_probs, sizeof(GroupedProblem) * count);
   if (e == hipSuccess && cap > 0) e = hipMalloc(&p->d_items, sizeof(WorkItem) * cap);
@@ -428,22 +536,33 @@ int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t
     if (q.m > 0 && q.n > 0 && (q.C == nullptr || (q.k > 0 && (!q.A || !q.B))))
       return set_error(GEMM_ENULL, "NULL matrix at problem " + std::to_string(i));
     // the captured work list runs each problem in the kernel its planned
-    // operands allowed: a problem planned with 16-byte transfers keeps them,
-    // so its new A and B must allow them too
-    if (plan->dprob_host[i].vec && !to_device(q, es).vec)
+    // operands allowed: a problem planned with 16-byte transfers of the
+    // caller's operands keeps them, so its new A and B must allow them too
+    // (a packed problem's copies take any alignment)
+    if (plan->pack_job[i] < 0 && plan->dprob_host[i].vec && !to_device(q, es).vec)
       return set_error(GEMM_EINVAL, "problem " + std::to_string(i) +
                                         " was planned with 16-byte aligned operands; the new A or "
                                         "B is not 16-byte aligned");
   }
   for (int32_t i = 0; i < count; ++i) {
-    const int32_t planned = plan->dprob_host[i].vec;
     plan->probs[i] = probs[i];
-    plan->dprob_host[i] = to_device(probs[i], es);
-    plan->dprob_host[i].vec = planned;   // the work list's split stays as captured
+    const int32_t pj = plan->pack_job[i];
+    if (pj >= 0) {   // the copies stay; their sources and C move
+      plan->jobs[pj].src = probs[i].A;
+      plan->jobs[pj + 1].src = probs[i].B;
+      plan->dprob_host[i].C = probs[i].C;
+    } else {
+      const int32_t planned = plan->dprob_host[i].vec;
+      plan->dprob_host[i] = to_device(probs[i], es);
+      plan->dprob_host[i].vec = planned;   // the work list's split stays as captured
+    }
   }
   if (count > 0) {
     hipError_t e = hipMemcpy(plan->d_probs, plan->dprob_host.data(),
                              sizeof(GroupedProblem) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plan->jobs.empty())
+      e = hipMemcpy(plan->d_jobs, plan->jobs.data(), sizeof(PackJob) * plan->jobs.size(),
+                    hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload problems");
   }
   return GEMM_OK;

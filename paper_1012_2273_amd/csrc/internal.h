@@ -81,15 +81,31 @@ struct WorkItem {                // one output tile
   int32_t cfg;                   // tile config id
   int32_t tm, tn;                // tile coordinates
 };
-// items[0, n_vec) belong to problems with 16-byte operands, the n_scalar
-// items after them to the others; each group has its own persistent kernel
-// and queue counter (counter[0] and counter[kCounterStride]).
-constexpr int kCounterStride = 16;
-hipError_t launch_grouped(int prec, const GroupedProblem *probs, const WorkItem *items,
-                          int32_t n_vec, int32_t n_scalar, uint32_t *counter, int grid,
-                          hipStream_t stream);
+// The work list holds three groups of items, each run by its own persistent
+// kernel with its own queue counter (counter[q * kCounterStride], q = 0, 1,
+// 2): problems whose own operands allow 16-byte transfers, packed problems
+// (their plan-owned copies do), and the rest (register path).
+constexpr int kCounterStride = 16, kQueues = 3;
+hipError_t launch_grouped(int prec, bool vec, const GroupedProblem *probs, const WorkItem *items,
+                          int32_t n_items, uint32_t *counter, int grid, hipStream_t stream);
 hipError_t launch_counter_reset(uint32_t *counter, hipStream_t stream);
 int grouped_max_grid(int prec);   // persistent workgroups that fit the device
+
+// Copy of one operand into a plan-owned buffer whose rows allow 16-byte
+// transfers: dst (drows x dcols, pitch dld, 16-byte aligned, dcols and dld
+// whole vectors) receives src (rows x cols, pitch sld, any alignment) with
+// zeros in [rows, drows) x [cols, dcols). Workgroups
+// [first_block, first_block + ceil(drows / kPackRows)) copy it.
+struct PackJob {
+  const void *src;
+  void *dst;
+  int64_t sld, dld;
+  int64_t rows, cols, drows, dcols;
+  int64_t first_block;
+};
+constexpr int kPackRows = 8;
+hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks,
+                       hipStream_t stream);
 
 // Error bookkeeping (thread-local detail string).
 int set_error(int code, const std::string &detail);

@@ -41,8 +41,9 @@ template <int P> __host__ __device__ constexpr int grouped_lds() {
 // Same path choice as a single launch: direct-to-LDS when the operands allow
 // 16-byte transfers and the shape's K-tile splits into whole 1 KiB transfers
 // per loader wave, else registers.
-// Problems with and without 16-byte operands go to two kernels (VEC), which
-// keeps each kernel's register allocation to the paths it runs.
+// Problems with 16-byte operands (their own, or the plan's packed copies)
+// and the rest run in different kernels (VEC), which keeps each kernel's
+// register allocation to the paths it runs.
 template <int P, class S, bool VEC>
 __device__ __forceinline__ void run_item(const GemmArgs &g, const WorkItem &w, char *smem) {
   const int64_t m0 = (int64_t)w.tm * S::BM, n0 = (int64_t)w.tn * S::BN;
@@ -83,10 +84,7 @@ gemm_grouped_kernel(const GroupedProblem *__restrict__ probs, const WorkItem *__
 }
 
 __global__ void counter_reset_kernel(uint32_t *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    counter[0] = 0u;
-    counter[kCounterStride] = 0u;
-  }
+  if (threadIdx.x < kQueues && blockIdx.x == 0) counter[threadIdx.x * kCounterStride] = 0u;
 }
 
 hipError_t launch_counter_reset(uint32_t *counter, hipStream_t stream) {
@@ -94,34 +92,71 @@ hipError_t launch_counter_reset(uint32_t *counter, hipStream_t stream) {
   return hipGetLastError();
 }
 
-template <int P>
-static hipError_t launch_pair(const GroupedProblem *probs, const WorkItem *items, int32_t n_vec,
-                              int32_t n_scalar, uint32_t *counter, int grid, hipStream_t stream) {
-  if (n_vec > 0) {
-    hipLaunchKernelGGL((gemm_grouped_kernel<P, true>), dim3(grid), dim3(GNT), 0, stream, probs,
-                       items, n_vec, counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (n_scalar > 0) {
-    hipLaunchKernelGGL((gemm_grouped_kernel<P, false>), dim3(grid), dim3(GNT), 0, stream, probs,
-                       items + n_vec, n_scalar, counter + kCounterStride);
-    return hipGetLastError();
-  }
-  return hipSuccess;
+hipError_t launch_grouped(int prec, bool vec, const GroupedProblem *probs, const WorkItem *items,
+                          int32_t n_items, uint32_t *counter, int grid, hipStream_t stream) {
+  if (grid <= 0 || n_items <= 0) return hipSuccess;
+  const dim3 g(grid), b(GNT);
+  if (prec == PREC_F64 && vec)
+    hipLaunchKernelGGL((gemm_grouped_kernel<PREC_F64, true>), g, b, 0, stream, probs, items, n_items, counter);
+  else if (prec == PREC_F64)
+    hipLaunchKernelGGL((gemm_grouped_kernel<PREC_F64, false>), g, b, 0, stream, probs, items, n_items, counter);
+  else if (prec == PREC_F32 && vec)
+    hipLaunchKernelGGL((gemm_grouped_kernel<PREC_F32, true>), g, b, 0, stream, probs, items, n_items, counter);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL((gemm_grouped_kernel<PREC_F32, false>), g, b, 0, stream, probs, items, n_items, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
-hipError_t launch_grouped(int prec, const GroupedProblem *probs, const WorkItem *items,
-                          int32_t n_vec, int32_t n_scalar, uint32_t *counter, int grid,
-                          hipStream_t stream) {
-  if (grid <= 0) return hipSuccess;
-  switch (prec) {
-    case PREC_F64:
-      return launch_pair<PREC_F64>(probs, items, n_vec, n_scalar, counter, grid, stream);
-    case PREC_F32:
-      return launch_pair<PREC_F32>(probs, items, n_vec, n_scalar, counter, grid, stream);
+// The operand copy that lets a problem whose rows are not 16-byte multiples
+// use the direct-to-LDS kernel. A workgroup copies kPackRows destination rows
+// of one job (found by binary search over the jobs' first blocks), each wave
+// whole rows: lane l gathers the V elements of 16-byte destination vectors
+// l, l + 64, ... with element loads (a wave reads 64 V consecutive elements)
+// and stores each vector at once. Memory-bound: rows * cols elements read,
+// drows * dcols written per job.
+template <typename E>
+__global__ void __launch_bounds__(256)
+pack_kernel(const PackJob *__restrict__ jobs, int32_t n_jobs) {
+  constexpr int V = 16 / (int)sizeof(E);
+  typedef E Vec __attribute__((ext_vector_type(V)));
+  const int64_t b = blockIdx.x;
+  int32_t lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) / 2;
+    if (jobs[mid].first_block <= b) lo = mid; else hi = mid - 1;
   }
-  return hipErrorInvalidValue;
+  const PackJob j = jobs[lo];
+  const int64_t r0 = (b - j.first_block) * kPackRows;
+  const int wave = (int)(threadIdx.x / 64), lane = (int)(threadIdx.x % 64);
+  for (int rr = wave; rr < kPackRows && r0 + rr < j.drows; rr += 4) {
+    const int64_t r = r0 + rr;
+    const bool in = r < j.rows;
+    const E *s = reinterpret_cast<const E *>(j.src) + (in ? r * j.sld : 0);
+    E *d = reinterpret_cast<E *>(j.dst) + r * j.dld;
+    for (int64_t c = (int64_t)lane * V; c < j.dcols; c += 64 * V) {
+      Vec v;
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[e] = (in && c + e < j.cols) ? s[c + e] : (E)0;
+      *reinterpret_cast<Vec *>(d + c) = v;
+    }
+  }
+}
+
+hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks,
+                       hipStream_t stream) {
+  if (n_jobs <= 0 || blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(pack_kernel<double>, dim3((uint32_t)blocks), dim3(256), 0, stream, jobs,
+                       n_jobs);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL(pack_kernel<float>, dim3((uint32_t)blocks), dim3(256), 0, stream, jobs,
+                       n_jobs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 int grouped_max_grid(int prec) {

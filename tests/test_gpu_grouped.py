@@ -2,8 +2,12 @@
 
 512 independent square products, N log-uniform in [10, 2000], in binary64
 and binary32. Every problem equals the single-product kernel at the same
-tile shape bit for bit (same tiles, same reduction order), and the oracle
-checks every problem (full product for N <= 256, sampled entries above).
+tile shape bit for bit (same tiles, same reduction order): problems whose
+rows are whole 16-byte vectors against a launch on their own operands,
+packed problems (the plan copies their operands into zero-padded 16-byte
+rows) against a launch on padded copies, and with packing off against a
+launch on their own operands again; the oracle checks every problem (full
+product for N <= 256, sampled entries above).
 """
 import os
 
@@ -42,6 +46,36 @@ def _batch(count, dtype, seed=3_000_000):
     return sizes, probs
 
 
+def _vec_ok(A, B):
+    """Both operands allow 16-byte transfers (the plan's test)."""
+    v = 16 // A.element_size()
+    return (A.data_ptr() % 16 == 0 and B.data_ptr() % 16 == 0 and A.stride(0) % v == 0
+            and B.stride(0) % v == 0 and A.shape[1] % v == 0 and B.shape[1] % v == 0)
+
+
+def _single_like_plan(G, A, B, cfg, packed):
+    """One gemm_plain launch at tile config `cfg` computing what the plan
+    computes for (A, B): on the operands themselves, or on zero-padded
+    copies with 16-byte rows (the packed form), keeping the first n columns."""
+    torch = _torch()
+    n = B.shape[1]
+    if packed:
+        v = 16 // A.element_size()
+        m, k = A.shape
+        kp, np_ = -(-k // v) * v, -(-n // v) * v
+        Ap = torch.zeros((m, kp), dtype=A.dtype, device=A.device)
+        Ap[:, :k] = A
+        Bp = torch.zeros((kp, np_), dtype=B.dtype, device=B.device)
+        Bp[:k, :n] = B
+        A, B = Ap, Bp
+    G.force_tile_config(cfg)
+    try:
+        C = G.gemm_plain(A, B)
+    finally:
+        G.force_tile_config(-1)
+    return C[:, :n]
+
+
 def _check_against_oracle(sizes, probs, Cs, tol, max_full=256):
     worst = 0.0
     for i, (n, (A, B)) in enumerate(zip(sizes, probs)):
@@ -77,13 +111,15 @@ def test_batch_512_graph_autotuned(G, tname, tmp_path):
 
     # bitwise equal to single-product launches at the policy's tile shape
     names = G.tile_configs()
+    n_packed = 0
     for i in range(0, 512, 7):
         cfg = names.index(policy[size_class(int(sizes[i]), int(sizes[i]))])
-        G.force_tile_config(cfg)
-        Ci = G.gemm_plain(As[i], Bs[i])
-        G.force_tile_config(-1)
+        packed = not _vec_ok(As[i], Bs[i])
+        n_packed += packed
+        Ci = _single_like_plan(G, As[i], Bs[i], cfg, packed)
         torch.cuda.synchronize()
-        assert torch.equal(Ci, Cs[i]), i
+        assert torch.equal(Ci, Cs[i]), (i, packed)
+    assert n_packed > 0
 
     # graph replays with eager work in between: every replay identical
     first = [C.clone() for C in Cs]
@@ -101,6 +137,20 @@ def test_batch_512_graph_autotuned(G, tname, tmp_path):
     assert plan2.info()[1] == policy
     plan2.close()
     plan.close()
+
+    # packing off: the problems without 16-byte rows run on the register
+    # path, bit for bit as a single launch on their own operands
+    plan3 = G.GroupedPlan(As, Bs, tune_cache=cache, autotune=True, pack=False)
+    assert plan3.info()[1] == policy
+    Cs3 = plan3.run()
+    torch.cuda.synchronize()
+    _check_against_oracle(sizes, probs, Cs3, tol)
+    for i in range(0, 512, 11):
+        cfg = names.index(policy[size_class(int(sizes[i]), int(sizes[i]))])
+        Ci = _single_like_plan(G, As[i], Bs[i], cfg, False)
+        torch.cuda.synchronize()
+        assert torch.equal(Ci, Cs3[i]), i
+    plan3.close()
 
 
 def test_plan_update_new_pointers(G):
@@ -145,21 +195,28 @@ def test_plan_update_rejects_misaligned_views(G):
     plan.run()
     torch.cuda.synchronize()
     assert oracle.relerr_fro(C0.cpu().numpy(), oracle.gemm(A, B)) <= 1e-12
-    # an odd-sized problem is planned for any alignment and takes the view
+    # an odd-sized problem (packed, or on the register path) is planned for
+    # any alignment and takes the view; a packed plan reads the new pointers
+    # in its next run's copies
     m = 63
     A3, B3 = inputs.uniform_square(m, 506)
     A3d, B3d = dev(A3, torch), dev(B3, torch)
-    plan3 = G.GroupedPlan([A3d], [B3d])
     flat3 = torch.zeros(m * m + 1, dtype=torch.float64, device="cuda:0")
     view3 = flat3[1:].view(m, m)
-    view3.copy_(A3d)
-    C3 = torch.empty((m, m), dtype=torch.float64, device="cuda:0")
-    plan3.update([view3], [B3d], [C3])
-    plan3.run()
-    torch.cuda.synchronize()
-    assert oracle.relerr_fro(C3.cpu().numpy(), oracle.gemm(A3, B3)) <= 1e-12
+    for pack in (True, False):
+        plan3 = G.GroupedPlan([A3d], [B3d], pack=pack)
+        view3.copy_(2.0 * A3d)
+        C3 = torch.empty((m, m), dtype=torch.float64, device="cuda:0")
+        plan3.update([view3], [B3d], [C3])
+        plan3.run()
+        torch.cuda.synchronize()
+        assert oracle.relerr_fro(C3.cpu().numpy(), oracle.gemm(2.0 * A3, B3)) <= 1e-12, pack
+        view3.copy_(A3d)
+        plan3.run()
+        torch.cuda.synchronize()
+        assert oracle.relerr_fro(C3.cpu().numpy(), oracle.gemm(A3, B3)) <= 1e-12, pack
+        plan3.close()
     plan.close()
-    plan3.close()
 
 
 def test_uncaptured_and_edge_problems(G):
@@ -203,29 +260,55 @@ def test_grouped_integer_bit_exact(G):
     plan.close()
 
 
+def _offset_view(X, torch, lead_pad, base_elems):
+    """X's values in a view with row pitch cols + lead_pad, starting
+    base_elems elements past a 256-byte aligned allocation."""
+    r, c = X.shape
+    flat = torch.zeros(base_elems + r * (c + lead_pad), dtype=X.dtype, device=X.device)
+    v = flat[base_elems:].view(r, c + lead_pad)[:, :c]
+    v.copy_(X)
+    return v
+
+
+@pytest.mark.parametrize("pack", [True, False], ids=["pack", "nopack"])
 @pytest.mark.parametrize("tname", ["f64", "f32"])
-def test_grouped_unaligned_rows_every_edge(G, tname):
+def test_grouped_unaligned_rows_every_edge(G, tname, pack):
     """Problems whose rows are not whole 16-byte vectors (odd binary64
-    sizes, binary32 sizes not multiples of 4) run in the persistent kernel's
-    register path: ragged M, N and K edges, single rows and columns, K
-    shorter than a K-tile; each against the oracle, and integer entries bit
-    for bit."""
+    sizes, binary32 sizes not multiples of 4, offset views and padded
+    pitches) are packed into 16-byte rows, or with packing off run in the
+    persistent kernel's register path: ragged M, N and K edges, single rows
+    and columns, K shorter than a K-tile; each against the oracle, and
+    integer entries bit for bit."""
     torch = _torch()
     dt = np.float64 if tname == "f64" else np.float32
     tol = 1e-12 if tname == "f64" else 1e-5
     shapes = [(33, 65, 17), (129, 1, 3), (1, 127, 255), (257, 255, 129), (131, 67, 1001),
-              (67, 133, 5), (255, 257, 258), (9, 7, 1)]
+              (67, 133, 5), (255, 257, 258), (9, 7, 1), (130, 66, 200), (64, 128, 96)]
+    # the last two have 16-byte rows; given as views they are not 16-byte
+    # operands any more (base 1 element off, pitch padded by 3 elements)
+    views = {8: (3, 1), 9: (0, 1)}
     As, Bs, host = [], [], []
     for i, (m, n, k) in enumerate(shapes):
         A, B = inputs.uniform_mnk(m, n, k, 880 + i, dtype=dt)
         host.append((A, B))
-        As.append(dev(A, torch))
-        Bs.append(dev(B, torch))
-    plan = G.GroupedPlan(As, Bs)
+        Ad, Bd = dev(A, torch), dev(B, torch)
+        if i in views:
+            Ad = _offset_view(Ad, torch, *views[i])
+        As.append(Ad)
+        Bs.append(Bd)
+    assert not any(_vec_ok(A, B) for A, B in zip(As, Bs))
+    plan = G.GroupedPlan(As, Bs, pack=pack)
     Cs = plan.run()
     torch.cuda.synchronize()
     for (A, B), C in zip(host, Cs):
         assert oracle.relerr_fro(C.cpu().double().numpy(), oracle.gemm(A, B)) <= tol
+    # replays recopy: new values in the same operands
+    for A in As:
+        A.mul_(-1.0)
+    Cs = plan.run()
+    torch.cuda.synchronize()
+    for (A, B), C in zip(host, Cs):
+        assert oracle.relerr_fro(C.cpu().double().numpy(), oracle.gemm(-A, B)) <= tol
     plan.close()
     # integer entries: exact
     As, Bs, host = [], [], []
@@ -235,7 +318,7 @@ def test_grouped_unaligned_rows_every_edge(G, tname):
         host.append((A, B))
         As.append(dev(A, torch))
         Bs.append(dev(B, torch))
-    plan = G.GroupedPlan(As, Bs)
+    plan = G.GroupedPlan(As, Bs, pack=pack)
     Cs = plan.run()
     torch.cuda.synchronize()
     for (A, B), C in zip(host, Cs):
