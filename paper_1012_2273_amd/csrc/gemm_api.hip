@@ -117,22 +117,46 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
       if (t128 > cus) return CFG_128x128;
       if (t128 >= big) return CFG_128x64_K2;
       return t128 >= mid ? CFG_64x64_K2 : CFG_32x32;
-    // 16-bit: the 128 x 128 tile with loader waves holds a CU by itself (its
-    // ring takes 128 KiB of LDS), so it runs where one round covers every
-    // tile; from there to two tiles per CU the 8-wave tile, three of whose
-    // workgroups share a CU (bf16 N = 2500: 154 us with the loader tile in
-    // two rounds)
+    // 16-bit, measured on MI355X with random operands (TFLOP/s, the tile the
+    // rule takes against the best other): the 128 x 128 tile with loader
+    // waves holds a CU by itself (its ring takes 128 KiB of LDS) and still
+    // leads from about a quarter of a tile per CU up, also where its tiles
+    // take a second, partial round -- bf16 N = 1200 196 against 149
+    // (64 x 64), 2600 615 against 568 (the 8-wave tile, three of which share
+    // a CU), 2800 721 against 608 -- and bf16 takes the 128 x 256 tile from
+    // two tiles per CU (N = 3000 619 against 587, 4096 984 against 877). The
+    // split planes keep the loader tile at every size measured (nominal
+    // 2N^3/t: N = 1500 150 against 118, 3000 257 against 199, 4096 351
+    // against 334, 5000 315 against 280, 8192 345 against 329). Operands
+    // without 16-byte rows have no loader tile: fallback_rule below.
     case PREC_BF16:
-    case PREC_SPLIT:
       if (t128 >= 2 * cus) return CFG_128x256_W8;
-      if (t128 > cus) return CFG_128x128_W8;
-      if (t128 >= big) return CFG_128x128_K2_LD;
+      return t128 >= mid ? CFG_128x128_K2_LD : CFG_32x32;
+    case PREC_SPLIT:
+      if (2 * t128 >= cus) return CFG_128x128_K2_LD;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
-    default:  // three planes, fused splits
+    // the two-way split in registers (small products, see split_form): the
+    // loader tile from half a tile per CU (N = 1500 163 against 109)
+    case PREC_FSPLIT:
+      if (2 * t128 >= cus) return CFG_128x128_K2_LD;
+      return t128 >= mid ? CFG_64x64 : CFG_32x32;
+    default:  // three planes, three-way fused split
       if (t128 >= 2 * cus) return CFG_128x256_W8;
       if (t128 >= big) return CFG_128x128_W8;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
   }
+}
+
+// The 16-bit choice where the rule's tile is not offered (operands that
+// need the register path: rows that are not 16-byte multiples): the 8-wave
+// tile from about one tile per CU, three of whose workgroups share a CU.
+static int fallback_rule(int prec, int64_t m, int64_t n) {
+  const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
+  const int64_t cus = device_cus();
+  const int64_t big = cus * 200 / 256, mid = cus * 48 / 256;
+  if ((prec == PREC_BF16 || prec == PREC_SPLIT) && t128 >= 2 * cus) return CFG_128x256_W8;
+  if (t128 >= big) return CFG_128x128_W8;
+  return t128 >= mid ? CFG_64x64 : CFG_32x32;
 }
 
 // Workgroups one CU holds for a kernel, cached per device.
@@ -207,8 +231,9 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
     return forced;
   int pick = choose_rule(prec, m, n);
   // shapes offered on the direct-to-LDS path only (loader waves, 16-bit K
-  // split) step back to the 8-wave tile where the operands need the
-  // register path or the layout has no such kernel
+  // split) step back where the operands need the register path or the
+  // layout has no such kernel
+  if (!plain_offered(prec, layout, pick, vw)) pick = fallback_rule(prec, m, n);
   if (!plain_offered(prec, layout, pick, vw)) pick = CFG_128x128_W8;
   if (prec != PREC_F64 && prec != PREC_F32) return pick;
   const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
@@ -640,7 +665,13 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 // 70.8, 2500 145.6 / 157.0, 4096 455.8 / 448.3 (the loaders' register loads
 // of binary32 tiles keep pace with six products per tile, not with three).
 // So the three-way split takes it from half a tile per CU to three tiles
-// per CU, the two-way split keeps the two steps.
+// per CU, the two-way split keeps the two steps. With the plane products on
+// the loader tile (choose_rule) a second sweep gave, nominal TFLOP/s: the
+// two-way split in registers on the loader tile N = 1500 163 against 150
+// (two steps), 1800 220 against 215, 2600 260 against 273; the three-way
+// loader form N = 5000 176 against 161 (two steps, 128 x 256), 6144 197
+// against 182, 8192 201 against 194, but N = 4096 193 against 207: the
+// three-way split keeps the two steps from three to five tiles per CU.
 
 static int split_form(int np, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
                       const void *B, int64_t ldb) {
@@ -652,9 +683,11 @@ static int split_form(int np, int64_t m, int64_t n, int64_t k, const void *A, in
   if (f == FORM_REGISTERS) return vec ? FORM_REGISTERS : FORM_TWO_STEP;
   if (f == FORM_LOADERS) return loaders ? FORM_LOADERS : FORM_TWO_STEP;
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
-  const int64_t cus = device_cus();
+  const int64_t cus = device_cus(), big = cus * 200 / 256;
   if (vec && k <= 1024 && 2 * t128 <= cus) return FORM_REGISTERS;
-  if (np == 3 && loaders && 2 * t128 >= cus && t128 < 3 * cus) return FORM_LOADERS;
+  if (np == 2 && vec && 2 * t128 >= cus && t128 < big) return FORM_REGISTERS;
+  if (np == 3 && loaders && 2 * t128 >= cus && (t128 < 3 * cus || t128 >= 5 * cus))
+    return FORM_LOADERS;
   return FORM_TWO_STEP;
 }
 

@@ -97,12 +97,16 @@ def test_fused_equals_two_step_every_config(G, name):
 
 
 def test_form_rule(G):
-    """Which form the library takes: one launch only for small, aligned
-    products with a short K loop."""
+    """Which form the library takes: one launch for aligned products with a
+    short K loop that leave most CUs idle, and for aligned products of half
+    a 128 x 128 tile per CU up to about 200 tiles (on the loader-wave tile)."""
     torch = _torch()
     z = lambda r, c: torch.zeros((r, c), dtype=torch.float32, device="cuda:0")
     assert G.split_one_launch(z(1000, 1000), z(1000, 1000))
     assert G.split_one_launch(z(1024, 1024), z(1024, 1024))
+    assert not G.split_one_launch(z(1200, 1200), z(1200, 1200))      # long K, a few tiles
+    assert G.split_one_launch(z(1500, 1500), z(1500, 1500))          # 144 tiles
+    assert not G.split_one_launch(z(1800, 1800), z(1800, 1800))      # 225 tiles
     assert not G.split_one_launch(z(2000, 2000), z(2000, 2000))      # many tiles
     assert not G.split_one_launch(z(64, 2048), z(2048, 64))          # long K loop
     assert not G.split_one_launch(z(64, 63), z(63, 64))              # k not a multiple of 4
@@ -122,6 +126,23 @@ def test_fused_largest_one_launch_size(G, name):
     f = getattr(G, name)(Ad, Bd).cpu().numpy().astype(np.float64)
     err = oracle.relerr_fro(f, oracle.gemm_omp(A, B))
     say(f"{name} one launch n={n} relerr={err:.3e}")
+    assert err <= 1e-5
+
+
+def test_fused_loader_tile_n1500(G):
+    """The one-launch two-way split on the loader-wave tile (N = 1500, 144
+    tiles): bit for bit the two steps on the same tile, and the full binary64
+    oracle product within 1e-5."""
+    torch = _torch()
+    n = 1500
+    A, B = inputs.uniform_square(n, inputs.seed_for(2, n), dtype=np.float32)
+    Ad, Bd, Ap = dev(A, torch), dev(B, torch), _pitched(A, torch)
+    assert G.split_one_launch(Ad, Bd) and not G.split_one_launch(Ap, Bd)
+    f = G.gemm_split(Ad, Bd).cpu().numpy()
+    t = G.gemm_split(Ap, Bd).cpu().numpy()
+    assert np.array_equal(f.view(np.uint32), t.view(np.uint32))
+    err = oracle.relerr_fro(f.astype(np.float64), oracle.gemm_omp(A, B))
+    say(f"gemm_split one launch n={n} relerr={err:.3e}")
     assert err <= 1e-5
 
 
