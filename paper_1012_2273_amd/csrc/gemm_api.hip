@@ -672,6 +672,15 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 // loader form N = 5000 176 against 161 (two steps, 128 x 256), 6144 197
 // against 182, 8192 201 against 194, but N = 4096 193 against 207: the
 // three-way split keeps the two steps from three to five tiles per CU.
+// Up to one round of the loader tile the two-way split runs in registers:
+// with operands read from HBM (each call after a 512 MiB fill, no sync) it
+// took, us, N = 1800 61.4 against 61.9 for the two steps, 2000 66.7 against
+// 71.3, 2048 66.5 against 73.9 (the product's own operand reads overlap its
+// MFMAs, where the split step's pass over A and B does not); with operands
+// that stay in the Infinity Cache from call to call (the same A and B back
+// to back) the two steps are ahead at N = 2000 (61.9 against 65.9 us). From
+// the second round on the forms are level (N = 2200 119.8 against 119.5,
+// 2600 145.1 against 144.9) and the two steps stay.
 
 static int split_form(int np, int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
                       const void *B, int64_t ldb) {
@@ -683,9 +692,9 @@ static int split_form(int np, int64_t m, int64_t n, int64_t k, const void *A, in
   if (f == FORM_REGISTERS) return vec ? FORM_REGISTERS : FORM_TWO_STEP;
   if (f == FORM_LOADERS) return loaders ? FORM_LOADERS : FORM_TWO_STEP;
   const int64_t t128 = ((m + 127) / 128) * ((n + 127) / 128);
-  const int64_t cus = device_cus(), big = cus * 200 / 256;
+  const int64_t cus = device_cus();
   if (vec && k <= 1024 && 2 * t128 <= cus) return FORM_REGISTERS;
-  if (np == 2 && vec && 2 * t128 >= cus && t128 < big) return FORM_REGISTERS;
+  if (np == 2 && vec && 2 * t128 >= cus && t128 <= cus) return FORM_REGISTERS;
   if (np == 3 && loaders && 2 * t128 >= cus && (t128 < 3 * cus || t128 >= 5 * cus))
     return FORM_LOADERS;
   return FORM_TWO_STEP;

@@ -98,16 +98,17 @@ def test_fused_equals_two_step_every_config(G, name):
 
 def test_form_rule(G):
     """Which form the library takes: one launch for aligned products with a
-    short K loop that leave most CUs idle, and for aligned products of half
-    a 128 x 128 tile per CU up to about 200 tiles (on the loader-wave tile)."""
+    short K loop that leave most CUs idle, and for aligned products from half
+    a 128 x 128 tile per CU to one per CU (one round of the loader-wave tile)."""
     torch = _torch()
     z = lambda r, c: torch.zeros((r, c), dtype=torch.float32, device="cuda:0")
     assert G.split_one_launch(z(1000, 1000), z(1000, 1000))
     assert G.split_one_launch(z(1024, 1024), z(1024, 1024))
     assert not G.split_one_launch(z(1200, 1200), z(1200, 1200))      # long K, a few tiles
     assert G.split_one_launch(z(1500, 1500), z(1500, 1500))          # 144 tiles
-    assert not G.split_one_launch(z(1800, 1800), z(1800, 1800))      # 225 tiles
-    assert not G.split_one_launch(z(2000, 2000), z(2000, 2000))      # many tiles
+    assert G.split_one_launch(z(2000, 2000), z(2000, 2000))          # 256 tiles
+    assert G.split_one_launch(z(2048, 2048), z(2048, 2048))          # 256 tiles
+    assert not G.split_one_launch(z(2200, 2200), z(2200, 2200))      # a second round
     assert not G.split_one_launch(z(64, 2048), z(2048, 64))          # long K loop
     assert not G.split_one_launch(z(64, 63), z(63, 64))              # k not a multiple of 4
     assert not G.split_one_launch(z(64, 64), z(64, 62))              # n not a multiple of 4
@@ -129,12 +130,12 @@ def test_fused_largest_one_launch_size(G, name):
     assert err <= 1e-5
 
 
-def test_fused_loader_tile_n1500(G):
+@pytest.mark.parametrize("n", [1500, 2000])
+def test_fused_loader_tile(G, n):
     """The one-launch two-way split on the loader-wave tile (N = 1500, 144
-    tiles): bit for bit the two steps on the same tile, and the full binary64
-    oracle product within 1e-5."""
+    tiles; N = 2000, 256): bit for bit the two steps on the same tile, and the
+    full binary64 oracle product within 1e-5."""
     torch = _torch()
-    n = 1500
     A, B = inputs.uniform_square(n, inputs.seed_for(2, n), dtype=np.float32)
     Ad, Bd, Ap = dev(A, torch), dev(B, torch), _pitched(A, torch)
     assert G.split_one_launch(Ad, Bd) and not G.split_one_launch(Ap, Bd)
