@@ -188,16 +188,18 @@ int gemm_split(int64_t m, int64_t n, int64_t k,
                void *stream);
 
 /*
- * gemm_split_one_launch -- 1 if gemm_split and gemm_split3 with these
- * arguments run as one launch that splits each fragment in registers, 0 if
- * they run the split step and then the plane product (or if the arguments
- * are empty or null; nothing is validated or launched). The one-launch form
- * needs A and B 16-byte aligned with row pitches of a multiple of 16 bytes,
- * k and n multiples of 4, k <= 1024 and at most one 128 x 128 output tile
- * per two CUs of the current device: there the separate split step costs
- * more than repeating the conversion in every wave that reads a fragment.
- * Both forms give the same result bit for bit (Section 3.1, Algorithm 1 with
- * the split operands of gemm_split / gemm_split3).
+ * gemm_split_one_launch -- 1 if gemm_split with these arguments runs as one
+ * launch that splits each fragment in registers, 0 if it runs the split step
+ * and then the plane product (or if the arguments are empty or null; nothing
+ * is validated or launched). The in-register form needs A and B 16-byte
+ * aligned with row pitches of a multiple of 16 bytes, k and n multiples of
+ * 4, and either k <= 1024 with at most one 128 x 128 output tile per two CUs
+ * of the current device (gemm_split3 runs in registers there too), or from
+ * one tile per two CUs to one tile per CU (gemm_split only): there the
+ * separate split step's pass over A and B costs more than repeating the
+ * conversion in every wave that reads a fragment. All forms give the same
+ * result bit for bit (Section 3.1, Algorithm 1 with the split operands of
+ * gemm_split / gemm_split3).
  */
 int gemm_split_one_launch(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                           const float *B, int64_t ldb);
@@ -232,9 +234,14 @@ int gemm_split3_convert(int64_t rows, int64_t cols, const float *X, int64_t ldx,
  * bfloat16 matrix cores; the higher-accuracy variant of gemm_split.
  *   workspace  device memory of at least gemm_split3_workspace_size(m, n, k)
  *              bytes, owned by the caller, 16-byte aligned, not shared by
- *              overlapping calls. Small products run as one launch, as for
- *              gemm_split. After a two-step call it holds A_hi, A_mid, A_lo,
- *              B_hi, B_mid, B_lo in the layout gemm_split describes.
+ *              overlapping calls. Small products run as one launch that
+ *              splits in registers (k <= 1024, at most one tile per two CUs);
+ *              from one tile per two CUs up, except between three and five
+ *              tiles per CU, one launch whose loader waves split each tile
+ *              once into LDS (both need 16-byte rows, as gemm_split_one_launch
+ *              states); either leaves the workspace untouched. After a
+ *              two-step call it holds A_hi, A_mid, A_lo, B_hi, B_mid, B_lo
+ *              in the layout gemm_split describes.
  * Errors: EINVAL, ENULL, ELD, EWORKSPACE, EHIP.
  */
 int gemm_split3(int64_t m, int64_t n, int64_t k,
