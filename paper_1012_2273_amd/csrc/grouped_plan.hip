@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cctype>
 #include <cstdio>
 #include <cstring>
@@ -75,6 +76,7 @@ struct gemm_plan {
   g355::PackJob *d_jobs = nullptr;
   void *d_pack = nullptr;
   int64_t pack_blocks = 0;
+  int pack_grid = 0;          // workgroups of the copy launch (see pack_grid_for)
   // the copies run on a side stream beside the first queue's kernel
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -154,7 +156,7 @@ static int launch_direct(gemm_plan &p, hipStream_t s) {
     e = hipEventRecord(p.ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(p.side, p.ev_fork, 0);
     if (e == hipSuccess)
-      e = launch_pack(p.prec, p.d_jobs, (int32_t)p.jobs.size(), p.pack_blocks, p.side);
+      e = launch_pack(p.prec, p.d_jobs, (int32_t)p.jobs.size(), p.pack_blocks, p.pack_grid, p.side);
     if (e == hipSuccess) e = hipEventRecord(p.ev_join, p.side);
   }
   const WorkItem *it = p.d_items;
@@ -361,6 +363,34 @@ static GroupedProblem to_device(const gemm_problem &q, size_t es) {
   return d;
 }
 
+// Workgroups for the copies. They run beside the first queue's kernel (the
+// problems with 16-byte rows of their own), which leaves room on every CU
+// for a few copy workgroups; a full grid of them takes CU time and HBM from
+// that kernel (binary64 512-problem batch: the first queue 4.38 ms alone,
+// 5.02 beside 25398 copy workgroups). So the copies get just enough
+// workgroups to finish within about three quarters of the first queue's
+// estimated time: ~9 GB/s per copy workgroup beside the product (measured:
+// 3.7 GB in 6.4 ms on 64), the first queue at 65 (binary64) / 120 (binary32)
+// TFLOP/s. Measured replays (ms): binary64 10.77 with one workgroup per
+// block, 10.17 with 128, 10.28 with 256, 12.17 with 64 (the copies then
+// outlast the first queue); binary32 6.53 with one per block, 6.44 with
+// 1024, 7.54 with 128.
+static int pack_grid_for(const gemm_plan &p, size_t es) {
+  double flops0 = 0.0, bytes = 0.0;
+  for (size_t i = 0; i < p.probs.size(); ++i)
+    if (p.pack_job[i] < 0 && p.dprob_host[i].vec)
+      flops0 += 2.0 * (double)p.probs[i].m * (double)p.probs[i].n * (double)p.probs[i].k;
+  for (const PackJob &j : p.jobs)
+    bytes += (double)(j.rows * j.cols + j.drows * j.dcols) * (double)es;
+  const double rate = p.prec == PREC_F64 ? 65e12 : 120e12;
+  const double t0 = flops0 / rate;
+  if (t0 <= 0.0) return 0;                     // nothing to hide under: one per block
+  const double want = bytes / (0.75 * t0 * 9e9);
+  const int64_t lo = std::min<int64_t>(64, p.pack_blocks);
+  if (want >= (double)p.pack_blocks) return 0;
+  return (int)std::max<int64_t>(lo, (int64_t)std::ceil(want));
+}
+
 // Lays out the packed copies of every problem whose operands do not allow
 // 16-byte transfers (and whose product reads them: m, n, k > 0) in one
 // device buffer and points those problems at them: A' = m x k' and B' =
@@ -417,6 +447,7 @@ static int setup_packing(gemm_plan &p, size_t es) {
     blocks += (j.drows + kPackRows - 1) / kPackRows;
   }
   p.pack_blocks = blocks;
+  p.pack_grid = pack_grid_for(p, es);
   e = hipMemcpy(p.d_jobs, p.jobs.data(), sizeof(PackJob) * p.jobs.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "upload copy jobs");
   return GEMM_OK;

@@ -94,8 +94,9 @@ int grouped_max_grid(int prec);   // persistent workgroups that fit the device
 // Copy of one operand into a plan-owned buffer whose rows allow 16-byte
 // transfers: dst (drows x dcols, pitch dld, 16-byte aligned, dcols and dld
 // whole vectors) receives src (rows x cols, pitch sld, any alignment) with
-// zeros in [rows, drows) x [cols, dcols). Workgroups
-// [first_block, first_block + ceil(drows / kPackRows)) copy it.
+// zeros in [rows, drows) x [cols, dcols). Blocks [first_block, first_block +
+// ceil(drows / kPackRows)) of the copy launch copy it; `grid` workgroups
+// (0: one per block) walk the blocks.
 struct PackJob {
   const void *src;
   void *dst;
@@ -104,7 +105,7 @@ struct PackJob {
   int64_t first_block;
 };
 constexpr int kPackRows = 8;
-hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks,
+hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks, int grid,
                        hipStream_t stream);
 
 // Error bookkeeping (thread-local detail string).

@@ -110,50 +110,53 @@ hipError_t launch_grouped(int prec, bool vec, const GroupedProblem *probs, const
 }
 
 // The operand copy that lets a problem whose rows are not 16-byte multiples
-// use the direct-to-LDS kernel. A workgroup copies kPackRows destination rows
-// of one job (found by binary search over the jobs' first blocks), each wave
+// use the direct-to-LDS kernel. Block b copies kPackRows destination rows of
+// one job (found by binary search over the jobs' first blocks); a grid
+// smaller than the block count walks the blocks in strides. Each wave copies
 // whole rows: lane l gathers the V elements of 16-byte destination vectors
 // l, l + 64, ... with element loads (a wave reads 64 V consecutive elements)
 // and stores each vector at once. Memory-bound: rows * cols elements read,
 // drows * dcols written per job.
 template <typename E>
 __global__ void __launch_bounds__(256)
-pack_kernel(const PackJob *__restrict__ jobs, int32_t n_jobs) {
+pack_kernel(const PackJob *__restrict__ jobs, int32_t n_jobs, int64_t nblocks) {
   constexpr int V = 16 / (int)sizeof(E);
   typedef E Vec __attribute__((ext_vector_type(V)));
-  const int64_t b = blockIdx.x;
-  int32_t lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) / 2;
-    if (jobs[mid].first_block <= b) lo = mid; else hi = mid - 1;
-  }
-  const PackJob j = jobs[lo];
-  const int64_t r0 = (b - j.first_block) * kPackRows;
   const int wave = (int)(threadIdx.x / 64), lane = (int)(threadIdx.x % 64);
-  for (int rr = wave; rr < kPackRows && r0 + rr < j.drows; rr += 4) {
-    const int64_t r = r0 + rr;
-    const bool in = r < j.rows;
-    const E *s = reinterpret_cast<const E *>(j.src) + (in ? r * j.sld : 0);
-    E *d = reinterpret_cast<E *>(j.dst) + r * j.dld;
-    for (int64_t c = (int64_t)lane * V; c < j.dcols; c += 64 * V) {
-      Vec v;
+  for (int64_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    int32_t lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) / 2;
+      if (jobs[mid].first_block <= b) lo = mid; else hi = mid - 1;
+    }
+    const PackJob j = jobs[lo];
+    const int64_t r0 = (b - j.first_block) * kPackRows;
+    for (int rr = wave; rr < kPackRows && r0 + rr < j.drows; rr += 4) {
+      const int64_t r = r0 + rr;
+      const bool in = r < j.rows;
+      const E *s = reinterpret_cast<const E *>(j.src) + (in ? r * j.sld : 0);
+      E *d = reinterpret_cast<E *>(j.dst) + r * j.dld;
+      for (int64_t c = (int64_t)lane * V; c < j.dcols; c += 64 * V) {
+        Vec v;
 #pragma unroll
-      for (int e = 0; e < V; ++e) v[e] = (in && c + e < j.cols) ? s[c + e] : (E)0;
-      *reinterpret_cast<Vec *>(d + c) = v;
+        for (int e = 0; e < V; ++e) v[e] = (in && c + e < j.cols) ? s[c + e] : (E)0;
+        *reinterpret_cast<Vec *>(d + c) = v;
+      }
     }
   }
 }
 
-hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks,
+hipError_t launch_pack(int prec, const PackJob *jobs, int32_t n_jobs, int64_t blocks, int grid,
                        hipStream_t stream) {
   if (n_jobs <= 0 || blocks <= 0) return hipSuccess;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int64_t g = grid <= 0 || grid > blocks ? blocks : grid;
+  if (g > 0x7fffffffLL) return hipErrorInvalidValue;
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(pack_kernel<double>, dim3((uint32_t)blocks), dim3(256), 0, stream, jobs,
-                       n_jobs);
+    hipLaunchKernelGGL(pack_kernel<double>, dim3((uint32_t)g), dim3(256), 0, stream, jobs,
+                       n_jobs, blocks);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(pack_kernel<float>, dim3((uint32_t)blocks), dim3(256), 0, stream, jobs,
-                       n_jobs);
+    hipLaunchKernelGGL(pack_kernel<float>, dim3((uint32_t)g), dim3(256), 0, stream, jobs,
+                       n_jobs, blocks);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
