@@ -53,6 +53,7 @@ bool cfg_supported(int prec, int cfg) {
   if (cfg < 0 || cfg >= CFG_COUNT) return false;
   if (cfg == CFG_128x128_K2 || cfg == CFG_128x128_K2_LD)   // 16-bit, loaders: direct-to-LDS only
     return true;
+  if (cfg == CFG_128x128_W8) return true;   // also a grouped shape
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
   if (cfg == CFG_64x64_K4) return prec == PREC_F64;

@@ -27,7 +27,8 @@ enum TileCfg : int {
   CFG_32x32_K2 = 8, CFG_128x256_W8 = 9, CFG_64x64_K4 = 10, CFG_128x128_K2_LD = 11,
   CFG_COUNT = 12
 };
-constexpr int kGroupedCfgs[4] = {CFG_128x128_K2, CFG_128x64_K2, CFG_64x64_K2, CFG_32x32_K2};
+constexpr int kGroupedCfgs[5] = {CFG_128x128_K2, CFG_128x64_K2, CFG_64x64_K2, CFG_32x32_K2,
+                                 CFG_128x128_W8};
 bool cfg_grouped(int cfg);
 struct CfgInfo { int bm, bn; const char *name; };
 const CfgInfo &cfg_info(int id);

@@ -13,13 +13,14 @@
 namespace g355 {
 
 // The grouped shapes: 512 threads, two waves per output position each
-// taking half of every K-tile (the same shapes single launches offer under
-// the same ids, so a problem's tiles are computed bit for bit as a single
-// launch of that shape would compute them).
+// taking half of every K-tile, and the 8-wave 128 x 128 tile (the same
+// shapes single launches offer under the same ids, so a problem's tiles are
+// computed bit for bit as a single launch of that shape would compute them).
 using G128x128 = Shape<128, 128, 2, 2, 2>;
 using G128x64 = Shape<128, 64, 2, 2, 2>;
 using G64x64 = Shape<64, 64, 2, 2, 2>;
 using G32x32 = Shape<32, 32, 2, 2, 2>;
+using G128x128w8 = Shape<128, 128, 4, 2, 1>;
 constexpr int GNT = 512;
 
 template <int P, class S> __host__ __device__ constexpr int item_lds() {
@@ -34,8 +35,9 @@ template <int P, class S> __host__ __device__ constexpr int item_lds() {
 template <int P> __host__ __device__ constexpr int grouped_lds() {
   constexpr int a = item_lds<P, G128x128>(), b = item_lds<P, G128x64>();
   constexpr int c = item_lds<P, G64x64>(), d = item_lds<P, G32x32>();
-  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
-  return ab > cd ? ab : cd;
+  constexpr int e = item_lds<P, G128x128w8>();
+  constexpr int ab = a > b ? a : b, cd = c > d ? c : d, abcd = ab > cd ? ab : cd;
+  return abcd > e ? abcd : e;
 }
 
 // Same path choice as a single launch: direct-to-LDS when the operands allow
@@ -77,6 +79,7 @@ gemm_grouped_kernel(const GroupedProblem *__restrict__ probs, const WorkItem *__
       case CFG_128x128_K2: run_item<P, G128x128, VEC>(g, w, smem); break;
       case CFG_128x64_K2: run_item<P, G128x64, VEC>(g, w, smem); break;
       case CFG_64x64_K2: run_item<P, G64x64, VEC>(g, w, smem); break;
+      case CFG_128x128_W8: run_item<P, G128x128w8, VEC>(g, w, smem); break;
       default: run_item<P, G32x32, VEC>(g, w, smem); break;
     }
     __syncthreads();   // the next item's prologue reuses the LDS
