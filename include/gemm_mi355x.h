@@ -326,8 +326,9 @@ int gemm_grouped_run(gemm_plan *plan, void *stream);
  * runs in the kernel that reads them that way: its new A and B must be
  * 16-byte aligned as well (packed problems and, with GEMM_PLAN_NO_PACK, the
  * other problems take any alignment). Takes effect
- * for the next run without re-capture; synchronous copy. Nothing changes
- * when the call fails.
+ * for the next run without re-capture; synchronous copy, so no run of the
+ * plan may still be executing (synchronise its stream first). Nothing
+ * changes when the call fails.
  * Errors: ENULL, EINVAL (count or a size differs, or a 16-byte planned
  * problem gets operands that are not 16-byte aligned), EHIP. */
 int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t count);

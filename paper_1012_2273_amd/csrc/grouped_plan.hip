@@ -575,27 +575,40 @@ int gemm_grouped_plan_update(gemm_plan *plan, const gemm_problem *probs, int32_t
                                         " was planned with 16-byte aligned operands; the new A or "
                                         "B is not 16-byte aligned");
   }
+  // new device records first; the plan takes them once both uploads succeed
+  std::vector<GroupedProblem> dprob = plan->dprob_host;
+  std::vector<PackJob> jobs = plan->jobs;
   for (int32_t i = 0; i < count; ++i) {
-    plan->probs[i] = probs[i];
     const int32_t pj = plan->pack_job[i];
     if (pj >= 0) {   // the copies stay; their sources and C move
-      plan->jobs[pj].src = probs[i].A;
-      plan->jobs[pj + 1].src = probs[i].B;
-      plan->dprob_host[i].C = probs[i].C;
+      jobs[pj].src = probs[i].A;
+      jobs[pj + 1].src = probs[i].B;
+      dprob[i].C = probs[i].C;
     } else {
-      const int32_t planned = plan->dprob_host[i].vec;
-      plan->dprob_host[i] = to_device(probs[i], es);
-      plan->dprob_host[i].vec = planned;   // the work list's split stays as captured
+      const int32_t planned = dprob[i].vec;
+      dprob[i] = to_device(probs[i], es);
+      dprob[i].vec = planned;   // the work list's split stays as captured
     }
   }
   if (count > 0) {
-    hipError_t e = hipMemcpy(plan->d_probs, plan->dprob_host.data(),
-                             sizeof(GroupedProblem) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !plan->jobs.empty())
-      e = hipMemcpy(plan->d_jobs, plan->jobs.data(), sizeof(PackJob) * plan->jobs.size(),
+    hipError_t e = hipMemcpy(plan->d_probs, dprob.data(), sizeof(GroupedProblem) * count,
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess && !jobs.empty())
+      e = hipMemcpy(plan->d_jobs, jobs.data(), sizeof(PackJob) * jobs.size(),
                     hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload problems");
+    if (e != hipSuccess) {
+      // put the device records back as they were, so that nothing changes
+      hipMemcpy(plan->d_probs, plan->dprob_host.data(), sizeof(GroupedProblem) * count,
+                hipMemcpyHostToDevice);
+      if (!plan->jobs.empty())
+        hipMemcpy(plan->d_jobs, plan->jobs.data(), sizeof(PackJob) * plan->jobs.size(),
+                  hipMemcpyHostToDevice);
+      return hip_fail(e, "upload problems");
+    }
   }
+  plan->probs.assign(probs, probs + count);
+  plan->dprob_host.swap(dprob);
+  plan->jobs.swap(jobs);
   return GEMM_OK;
 }
 
