@@ -228,9 +228,11 @@ def _split_product(name, size_fn, A, B, C, workspace):
 
 
 def split_one_launch(A, B):
-    """True if gemm_split / gemm_split3 on these operands run as one launch
-    that splits each fragment in registers (small products), False if they
-    run the split step and then the plane product."""
+    """True if gemm_split on these operands runs as one launch that splits
+    each fragment in registers (small products, and up to one 128 x 128 tile
+    per CU on the loader-wave tile), False if it runs the split step and then
+    the plane product (gemm_split3 takes the in-register form only for the
+    small products; see gemm_split_one_launch in the C header)."""
     m, k = A.shape
     n = B.shape[1]
     if m == 0 or n == 0:

@@ -727,9 +727,10 @@ static int split_product(int np, int64_t m, int64_t n, int64_t k, const float *A
   if ((uintptr_t)workspace % 16 != 0)
     return set_error(GEMM_EWORKSPACE, "workspace must be 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  // Small products: one launch that splits each fragment in registers;
-  // one tile per CU: one launch whose loader waves split the tiles (both the
-  // same result bit for bit as the two steps, no planes in device memory).
+  // Small products and, two-way, up to one tile per CU: one launch that
+  // splits each fragment in registers; three-way from half a tile per CU:
+  // one launch whose loader waves split the tiles (both the same result bit
+  // for bit as the two steps, no planes in device memory).
   const int form = split_form(np, m, n, k, A, lda, B, ldb);
   if (form == FORM_REGISTERS) {
     GemmArgs a{m, n, k, A, lda, B, ldb, nullptr, nullptr, C, ldc};
