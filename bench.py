@@ -305,6 +305,48 @@ def ksplit_sweep(G, torch, dev, stream, inputs, ref):
     return out
 
 
+PRECISION_SIZES = (4096, 8192)
+
+
+def precision_sweep(G, torch, dev, stream, inputs, ref):
+    """The precision study's larger sizes: binary32 inputs (U[-1, 1]) as plain
+    binary32, plain bf16 (errors against the oracle of the rounded inputs,
+    ``rel_err``, and of the binary32 data, ``rel_err_path``), the two-way and
+    the three-way split (against the oracle of the binary32 data); nominal
+    2N^3/t, each path's median over back-to-back calls."""
+    out = {}
+    for n in PRECISION_SIZES:
+        print(f"sweep: precision paths N={n}", file=sys.stderr, flush=True)
+        A, B = inputs.uniform_square(n, inputs.seed_for(2, n), dtype=np.float32)
+        Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        Ab, Bb = Ad.to(torch.bfloat16), Bd.to(torch.bfloat16)
+        Cd = torch.empty((n, n), dtype=torch.float32, device=dev)
+        ws2 = torch.empty(G.gemm_split_workspace_size(n, n, n), dtype=torch.uint8, device=dev)
+        ws3 = torch.empty(G.gemm_split3_workspace_size(n, n, n), dtype=torch.uint8, device=dev)
+        fl = 2.0 * n ** 3
+        row = {}
+        for name, fn in (("fp32", lambda: G.gemm_plain(Ad, Bd, Cd)),
+                         ("bf16", lambda: G.gemm_plain(Ab, Bb, Cd)),
+                         ("split", lambda: G.gemm_split(Ad, Bd, Cd, ws2)),
+                         ("split3", lambda: G.gemm_split3(Ad, Bd, Cd, ws3))):
+            t = _median_call_ms(fn, torch, stream) * 1e-3
+            d = {"ms": round(t * 1e3, 4), "gflops": round(fl / t / 1e9, 2)}
+            if ref is not None:
+                fn()
+                torch.cuda.synchronize()
+                C = Cd.cpu().double().numpy()
+                if name == "bf16":
+                    Ar, Br = Ab.double().cpu().numpy(), Bb.double().cpu().numpy()
+                    d["rel_err"] = float(f"{ref.err(C, Ar, Br, seed=n + 1):.3e}")
+                    d["rel_err_path"] = float(f"{ref.err(C, A, B, seed=n + 1):.3e}")
+                else:
+                    d["rel_err"] = float(f"{ref.err(C, A, B, seed=n + 1):.3e}")
+            row[name] = d
+        out[str(n)] = row
+        del Ad, Bd, Ab, Bb, Cd, ws2, ws3
+    return out
+
+
 def transfer_inclusive(G, torch, dev, stream, A, B, C_resident, reps=10):
     """N = 2000 binary64 with the operands starting and ending in pinned host
     memory: H2D of A and B, the product, D2H of C on one stream."""
@@ -647,11 +689,12 @@ def main():
             errs[gpath] = worst
 
     # ------------------------------------------- outside the timed step loop
-    sweep = rect = ksw = None
+    sweep = rect = ksw = prec = None
     if not args.no_sweep:
         sweep = fp64_sweep(G, torch, dev, stream, inputs, ref, full={N: ref64})
         rect = rect_sweep(G, torch, dev, stream, inputs, ref)
         ksw = ksplit_sweep(G, torch, dev, stream, inputs, ref)
+        prec = precision_sweep(G, torch, dev, stream, inputs, ref)
     xfer = None
     if not args.no_transfer:
         A, B = host["fp64"]
@@ -712,6 +755,7 @@ def main():
         "sweep_fp64": sweep,
         "sweep_rect_fp64": rect,
         "sweep_ksplit_f32_bf16": ksw,
+        "sweep_precision": prec,
         "transfer_inclusive": xfer,
         "host": hinfo,
     }
