@@ -35,7 +35,8 @@ static const CfgInfo kCfgs[CFG_COUNT] = {{128, 128, "128x128"}, {128, 64, "128x6
                                          {128, 128, "128x128w8"}, {128, 128, "128x128k2"},
                                          {128, 64, "128x64k2"},   {64, 64, "64x64k2"},
                                          {32, 32, "32x32k2"},     {128, 256, "128x256w8"},
-                                         {64, 64, "64x64k4"},     {128, 128, "128x128k2ld"}};
+                                         {64, 64, "64x64k4"},     {128, 128, "128x128k2ld"},
+                                         {256, 256, "256x256w8"}};
 const CfgInfo &cfg_info(int id) { return kCfgs[id]; }
 
 // Tuning knobs (gemm_mi355x_tuning.h): per calling thread, so a test or a
@@ -56,6 +57,7 @@ bool cfg_supported(int prec, int cfg) {
   if (cfg == CFG_128x128_W8) return true;   // also a grouped shape
   if (cfg_grouped(cfg)) return prec == PREC_F64 || prec == PREC_F32;
   if (cfg == CFG_128x256_W8) return prec != PREC_F64 && prec != PREC_F32;
+  if (cfg == CFG_256x256_W8) return prec == PREC_BF16 || prec == PREC_SPLIT || prec == PREC_FSPLIT;
   if (cfg == CFG_64x64_K4) return prec == PREC_F64;
   return true;
 }
@@ -128,12 +130,18 @@ static int choose_rule(int prec, int64_t m, int64_t n) {
     // two tiles per CU (N = 3000 619 against 587, 4096 984 against 877). The
     // split planes keep the loader tile at every size measured (nominal
     // 2N^3/t: N = 1500 150 against 118, 3000 257 against 199, 4096 351
-    // against 334, 5000 315 against 280, 8192 345 against 329). Operands
-    // without 16-byte rows have no loader tile: fallback_rule below.
+    // against 334, 5000 315 against 280, 8192 345 against 329). From two
+    // tiles per CU both take the 256 x 256 tile, a third fewer operand bytes
+    // per flop than 128 x 256 (bf16 N = 4096 1037 against 1000, 5000 900
+    // against 821, 8192 1124 against 985, 6144 918 against 934; split N =
+    // 3000 266 against 254, 4096 396 against 354, 5000 333 against 311, 6144
+    // 314 against 304, 8192 385 against 346). Operands without 16-byte rows
+    // have no loader or 256 x 256 tile: fallback_rule below.
     case PREC_BF16:
-      if (t128 >= 2 * cus) return CFG_128x256_W8;
+      if (t128 >= 2 * cus) return CFG_256x256_W8;
       return t128 >= mid ? CFG_128x128_K2_LD : CFG_32x32;
     case PREC_SPLIT:
+      if (t128 >= 2 * cus) return CFG_256x256_W8;
       if (2 * t128 >= cus) return CFG_128x128_K2_LD;
       return t128 >= mid ? CFG_64x64 : CFG_32x32;
     // the two-way split in registers (small products, see split_form): the

@@ -263,6 +263,11 @@ constexpr int kRing16 = G355_RING16_KB * 1024;
 #ifndef G355_RING16_W8_KB
 #define G355_RING16_W8_KB 48
 #endif
+// The 256 x 256 tile holds one workgroup per CU (128 x 64 accumulators per
+// wave): its ring may take most of the LDS.
+#ifndef G355_RING16_BIG_KB
+#define G355_RING16_BIG_KB 128
+#endif
 // The 16-bit 128 x 128 tile with the K-tile split between wave pairs holds
 // one workgroup per CU: its ring takes most of the LDS.
 #ifndef G355_RING16_K2_KB
@@ -319,7 +324,8 @@ template <int P, class S, bool TA, bool TB> struct DmaPlan {
   // bounds the transfers a wave may leave outstanding.
   static constexpr int R16 = S::KS > 1 ? G355_RING16_K2_KB * 1024
                              : (S::NT >= 512 && S::BM * S::BN <= 128 * 128) ? G355_RING16_W8_KB * 1024
-                                                                           : kRing16;
+                             : S::BM * S::BN >= 256 * 256 ? G355_RING16_BIG_KB * 1024
+                                                          : kRing16;
   static constexpr int FIT = (T::KPL == 8 ? R16 : (S::NT <= 256 ? 72 : 144) * 1024) / STAGE;
   static constexpr int VMAX = 1 + 63 / (PER_WAVE > 0 ? PER_WAVE : 1);
   static constexpr int NS0 = T::KPL == 8 ? (FIT < 8 ? FIT : 8) : (FIT >= 3 ? 3 : 2);

@@ -21,11 +21,14 @@ struct GemmArgs;
 // 128 x 128); 64x64k4 to binary64 only (16 waves: four per output position,
 // each taking a quarter of every 32-deep K-tile). 128x128k2ld is 128x128k2
 // plus loader waves that issue every operand transfer (direct-to-LDS only).
+// 256x256w8 (8 waves of 128 x 64 outputs, 32-deep K-tiles, direct-to-LDS
+// only) is offered to the bfloat16-MFMA products: a third fewer operand
+// bytes per flop than 128 x 256.
 enum TileCfg : int {
   CFG_128x128 = 0, CFG_128x64 = 1, CFG_64x64 = 2, CFG_32x32 = 3,
   CFG_128x128_W8 = 4, CFG_128x128_K2 = 5, CFG_128x64_K2 = 6, CFG_64x64_K2 = 7,
   CFG_32x32_K2 = 8, CFG_128x256_W8 = 9, CFG_64x64_K4 = 10, CFG_128x128_K2_LD = 11,
-  CFG_COUNT = 12
+  CFG_256x256_W8 = 12, CFG_COUNT = 13
 };
 constexpr int kGroupedCfgs[5] = {CFG_128x128_K2, CFG_128x64_K2, CFG_64x64_K2, CFG_32x32_K2,
                                  CFG_128x128_W8};

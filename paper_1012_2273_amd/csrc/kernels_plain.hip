@@ -145,10 +145,10 @@ template <int P, class S, class F> static int by_layout(int layout, int vw, F &f
     if (layout != LAYOUT_NN || vw != 16) return -1;
     if constexpr (dma_ok<P, S, false, false>()) return f(KTag<P, S, false, false, 16>{});
     return -1;
-  } else if constexpr ((P == PREC_BF16 && S::KS > 1) || S::LDW > 0) {
+  } else if constexpr ((P == PREC_BF16 && S::KS > 1) || S::LDW > 0 || S::BM * S::BN >= 256 * 256) {
     // 16-bit K-split tiles exist on the direct-to-LDS path only (64-deep
     // K-tiles; the register path's 32-deep tiles do not split), and so do
-    // the shapes with loader waves
+    // the shapes with loader waves and the 256 x 256 tile
     if (vw != 16) return -1;
     switch (layout) {
       case LAYOUT_NN:
@@ -198,6 +198,7 @@ using S64x64k2 = Shape<64, 64, 2, 2, 2>;
 using S32x32k2 = Shape<32, 32, 2, 2, 2>;
 using S64x64k4 = Shape<64, 64, 2, 2, 4, 32>;   // 1024 threads
 using S128x256w8 = Shape<128, 256, 2, 4, 1, 32>;
+using S256x256w8 = Shape<256, 256, 2, 4, 1, 32>;
 #ifndef G355_LDW
 #define G355_LDW 4
 #endif
@@ -229,6 +230,13 @@ template <int P, class F> static int by_cfg(int layout, int cfg, int vw, F &f) {
         return by_layout<P, S128x256w8>(layout, vw, f);
       else
         return -1;   // bfloat16-MFMA products only (the host never picks it)
+    case CFG_256x256_W8:
+      // bf16 and the two-way split (whose three planes would not leave two
+      // stages of the ring: the three-way products stay off it, in both forms)
+      if constexpr (P == PREC_BF16 || P == PREC_SPLIT || P == PREC_FSPLIT)
+        return by_layout<P, S256x256w8>(layout, vw, f);
+      else
+        return -1;
   }
   return -1;
 }
