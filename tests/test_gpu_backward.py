@@ -133,10 +133,10 @@ def test_euler_identities_fp64(G):
     assert abs(np.sum(B * dB.cpu().numpy()) - L) < 1e-10
 
 
-@pytest.mark.parametrize("tname", ["f64", "f32"])
+@pytest.mark.parametrize("tname", ["f64", "f32", "bf16"])
 def test_transposed_tiles_equal_plain_on_transposed_copies(G, tname):
     torch = _torch()
-    tdt = torch.float64 if tname == "f64" else torch.float32
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[tname]
     n = 300
     A, B, W = inputs.uniform((n, n), 8, np.float64, 3)
     Ad, Bd, Wd = dev(A, torch, tdt), dev(B, torch, tdt), dev(W, torch, tdt)
@@ -149,6 +149,26 @@ def test_transposed_tiles_equal_plain_on_transposed_copies(G, tname):
         G.force_tile_config(-1)
         assert torch.equal(dA, pA), cfg
         assert torch.equal(dB, pB), cfg
+
+
+def test_backward_bf16_n3072_large_tiles(G):
+    """bf16 backward where the 16-bit rule takes the 256 x 256 tile for the
+    transposed-operand products (576 tiles of 128 x 128): sampled entries
+    against the binary64 oracle of the rounded inputs."""
+    torch = _torch()
+    n = 3072
+    A, B, W = inputs.uniform((n, n), inputs.seed_for(4, n), np.float32, 3)
+    Ab, Bb, Wb = (dev(X, torch).to(torch.bfloat16) for X in (A, B, W))
+    dA, dB = G.gemm_backward(Ab, Bb, Wb)
+    torch.cuda.synchronize()
+    Ar, Br, Wr = (oracle.bf16_to_f32(oracle.bf16_rne(X)) for X in (A, B, W))
+    r, c = sample_idx(n, n, 600, 5)
+    refA = oracle.gemm_entries(Wr, np.ascontiguousarray(Br.T), r, c)
+    refB = oracle.gemm_entries(np.ascontiguousarray(Ar.T), Wr, r, c)
+    eA = oracle.relerr_sampled(dA.cpu().double().numpy()[r, c], refA)
+    eB = oracle.relerr_sampled(dB.cpu().double().numpy()[r, c], refB)
+    say(f"bf16 backward n={n} sampled relerr dA={eA:.3e} dB={eB:.3e}")
+    assert eA <= 1e-5 and eB <= 1e-5
 
 
 def test_autograd_bf16_and_fp32_through_gemmfn(G):
