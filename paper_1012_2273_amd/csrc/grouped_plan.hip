@@ -4,19 +4,20 @@
 // A policy assigns one tile configuration to each size class of problems
 // (classes by max(m, n): <48, <96, <192, <384, <768, <1536, >=1536). The
 // planner turns a policy into the device work list: every tile of every
-// problem, sorted by decreasing work (tile area x k), so that the persistent
-// workgroups take the long tiles first and the short ones fill the tail.
+// problem, in three queues (internal.h), each sorted by decreasing work (tile
+// area x k), so that the persistent workgroups take the long tiles first and
+// the short ones fill the tail.
 // The tuner runs the persistent kernel on the caller's data for candidate
 // policies (one class at a time, largest class first, every tile config)
 // and keeps the fastest measured policy.
 //
 // Problems whose operands do not allow 16-byte transfers (binary64 rows of
 // odd length, binary32 rows not a multiple of 4, unaligned bases) are packed
-// unless the caller opts out: each run first copies their A and B into
-// plan-owned buffers with zero-padded, 16-byte rows (one launch for all of
-// them), and the persistent kernel reads those copies on the direct-to-LDS
-// path. The copy moves about as many bytes as the product reads and costs
-// less than the register path's element loads would.
+// unless the caller opts out: each run copies their A and B into plan-owned
+// buffers with zero-padded, 16-byte rows (one launch for all of them, on a
+// side stream beside the first queue's kernel, sized to finish under it),
+// and the second queue's kernel reads those copies on the direct-to-LDS
+// path instead of the register path's element loads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
