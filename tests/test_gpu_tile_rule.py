@@ -1,8 +1,9 @@
 """GPU parity at the sizes where the 16-bit tile rule takes the loader-wave
-tile in more than one round of workgroups, or the three-way loader form
-beyond five tiles per CU: bf16 (kernel-only, against the binary64 oracle of
-the rounded inputs), the two-way split and the three-way split (against the
-binary64 oracle of the binary32 inputs), sampled entries."""
+tile in more than one round of workgroups (N = 1200, 2600) or the 256 x 256
+tile (N = 3000), or the three-way loader form beyond five tiles per CU: bf16
+(kernel-only, against the binary64 oracle of the rounded inputs), the
+two-way split and the three-way split (against the binary64 oracle of the
+binary32 inputs), sampled entries."""
 import numpy as np
 import pytest
 
