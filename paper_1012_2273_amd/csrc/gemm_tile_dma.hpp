@@ -886,21 +886,40 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   // 3% that way and binary32 was level, so they keep ordinary stores.
   constexpr bool NTS = T::KPL == 8;
   Out *C = reinterpret_cast<Out *>(g.C);
+  // Interleaved MN blocks (ILB > 1) leave a lane holding ILB neighbouring
+  // columns of one row: they go out as one 16-byte store where C allows it
+  // (16-byte aligned base and row pitch, all ILB columns inside N), else
+  // element by element.
+  constexpr int VS = ILB * (int)sizeof(Out) == 16 ? ILB : 1;
+  typedef Out OutV __attribute__((ext_vector_type(VS)));
+  const bool cvec =
+      VS > 1 && ((reinterpret_cast<uintptr_t>(g.C) | (uintptr_t)(g.ldc * (int64_t)sizeof(Out))) & 15) == 0;
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     if (!owned(i)) continue;
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
+    for (int j = 0; j < FN; j += VS) {
       const int64_t col = n0 + wn * S::WTN + (j / ILB) * MB * ILB + ILB * lr + j % ILB;
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
         const int r = (q / GRP) * LGN * GRP + lgp * GRP + q % GRP;   // row within the block
         const int64_t row = m0 + wm * S::WTM + (i / ILA) * MB * ILA + ILA * r + i % ILA;
-        if (row < g.M && col < g.N) {
-          if constexpr (NTS)
-            __builtin_nontemporal_store((Out)acc[i][j][q], &C[row * g.ldc + col]);
-          else
-            C[row * g.ldc + col] = (Out)acc[i][j][q];
+        if (row >= g.M) continue;
+        if (VS > 1 && cvec && col + VS <= g.N) {
+          OutV v;
+#pragma unroll
+          for (int t = 0; t < VS; ++t) v[t] = (Out)acc[i][j + t][q];
+          *reinterpret_cast<OutV *>(&C[row * g.ldc + col]) = v;
+        } else {
+#pragma unroll
+          for (int t = 0; t < VS; ++t) {
+            if (col + t < g.N) {
+              if constexpr (NTS)
+                __builtin_nontemporal_store((Out)acc[i][j + t][q], &C[row * g.ldc + col + t]);
+              else
+                C[row * g.ldc + col + t] = (Out)acc[i][j + t][q];
+            }
+          }
         }
       }
     }

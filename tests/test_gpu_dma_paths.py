@@ -111,3 +111,34 @@ def test_split_every_config_bit_exact(G, shape):
         finally:
             G.force_tile_config(-1)
         assert np.array_equal(C.cpu().double().numpy(), ref), (shape, name)
+
+
+@pytest.mark.parametrize("tname", ["f64", "f32"])
+@pytest.mark.parametrize("coff,pad", [((0, 0), 8), ((1, 2), 8), ((0, 1), 8), ((0, 0), 1), ((3, 0), 5)])
+def test_plain_nn_output_views_every_config(G, tname, coff, pad):
+    """C as a view into a larger buffer with operands on the direct-to-LDS
+    path: a 16-byte aligned base and pitch (interleaved neighbouring columns
+    leave in one 16-byte store), and bases or pitches that are not (element
+    stores). Every config is bit-exact against the oracle and the buffer's
+    margin stays untouched."""
+    torch = _torch()
+    m, n, k = 200, 264, 136
+    A, B = _ints((m, k), 41), _ints((k, n), 43)
+    ref = oracle.gemm(A, B)
+    Ad, Bd = dev(A, torch, _tdt(tname)), dev(B, torch, _tdt(tname))
+    r0, c0 = coff
+    for cfg, name in enumerate(G.tile_configs()):
+        say(f"dma plain {tname} C view {coff} pad {pad} cfg={name}")
+        Cbig = torch.zeros((m + r0 + 1, n + pad), dtype=_tdt(tname), device="cuda:0")
+        Cv = Cbig[r0:r0 + m, c0:c0 + n]
+        G.force_tile_config(cfg)
+        try:
+            G.gemm_plain(Ad, Bd, Cv)
+            torch.cuda.synchronize()
+        finally:
+            G.force_tile_config(-1)
+        got = Cv.cpu().double().numpy()
+        assert np.array_equal(got, ref), (tname, coff, pad, name, np.abs(got - ref).max())
+        mask = torch.ones_like(Cbig, dtype=torch.bool)
+        mask[r0:r0 + m, c0:c0 + n] = False
+        assert torch.count_nonzero(Cbig[mask]).item() == 0, (tname, coff, pad, name)
