@@ -887,13 +887,14 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs &g, int64_t m0, int
   constexpr bool NTS = T::KPL == 8;
   Out *C = reinterpret_cast<Out *>(g.C);
   // Interleaved MN blocks (ILB > 1) leave a lane holding ILB neighbouring
-  // columns of one row: they go out as one 16-byte store where C allows it
-  // (16-byte aligned base and row pitch, all ILB columns inside N), else
-  // element by element.
-  constexpr int VS = ILB * (int)sizeof(Out) == 16 ? ILB : 1;
+  // columns of one row: they go out as one 8- or 16-byte store where C
+  // allows it (base and row pitch aligned to the store, all ILB columns
+  // inside N), else element by element.
+  constexpr int VB = ILB * (int)sizeof(Out);
+  constexpr int VS = (VB == 8 || VB == 16) ? ILB : 1;
   typedef Out OutV __attribute__((ext_vector_type(VS)));
-  const bool cvec =
-      VS > 1 && ((reinterpret_cast<uintptr_t>(g.C) | (uintptr_t)(g.ldc * (int64_t)sizeof(Out))) & 15) == 0;
+  const bool cvec = VS > 1 && ((reinterpret_cast<uintptr_t>(g.C) |
+                                (uintptr_t)(g.ldc * (int64_t)sizeof(Out))) & (VB - 1)) == 0;
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     if (!owned(i)) continue;
