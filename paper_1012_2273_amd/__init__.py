@@ -55,22 +55,41 @@ def _out_dtype(code):
 
 
 def _mat(t, name):
-    """(ptr, ld) of a row-major 2-D device tensor (unit column stride)."""
-    if t.dim() != 2:
+    """(ptr, ld) of a row-major 2-D device tensor (unit column stride); the
+    pointer as a plain int (0 for an empty matrix), which ctypes passes as a
+    void pointer. Each tensor attribute is read once: at small N the
+    binding's own time is most of a call's."""
+    shape = t.shape
+    if len(shape) != 2:
         raise GemmArgError(_lib.GEMM_EINVAL, name, "expected a 2-D tensor")
     if not t.is_cuda:
         raise GemmArgError(_lib.GEMM_EINVAL, name, "expected a device tensor")
-    if t.numel() == 0:
-        return ctypes.c_void_p(0), int(max(t.shape[1], 1))
-    if t.shape[1] > 1 and t.stride(1) != 1:
+    r, c = shape
+    if r == 0 or c == 0:
+        return 0, int(max(c, 1))
+    s0, s1 = t.stride()
+    if c > 1 and s1 != 1:
         raise GemmArgError(_lib.GEMM_ELD, name, "columns must be contiguous (stride 1)")
-    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
-    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), int(ld)
+    return t.data_ptr(), int(s0 if r > 1 else c)
+
+
+_raw_stream = None   # the current-stream query, chosen on first use
 
 
 def _stream(t):
-    torch = _torch()
-    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+    """The current stream of t's device as a raw pointer (torch's C-level
+    query when it has one: a tenth of a microsecond against about two for
+    building a Stream object)."""
+    global _raw_stream
+    if _raw_stream is None:
+        torch = _torch()
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            _raw_stream = lambda dev: raw(dev.index if dev.index is not None
+                                          else torch.cuda.current_device())
+        else:
+            _raw_stream = lambda dev: torch.cuda.current_stream(dev).cuda_stream
+    return _raw_stream(t.device)
 
 
 def _check_out(C, shape, dtype, like, where, name="C"):
