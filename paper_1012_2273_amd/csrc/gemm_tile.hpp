@@ -215,6 +215,12 @@ template <int P, class S> __host__ __device__ constexpr int bk_of() {
   } else if constexpr (P == PREC_F64) {
     return (S::BM * S::BN >= 128 * 128 && S::NT >= 512) || (S::BM * S::BN <= 32 * 32 && S::KS == 1)
                ? 32 : 16;
+  } else if constexpr ((P == PREC_F32 || P == PREC_BF16) && S::BM * S::BN <= 32 * 32 &&
+                       S::KS == 1 && S::NT == 256) {
+    // the 4-wave 32 x 32 tile of the small products, for the same reason as
+    // binary64's: binary32 N = 500 9.4 -> 8.1-8.4 us, N = 700 16.0 -> 13.6;
+    // bf16 N = 600 10.1 -> 7.8-8.2, level elsewhere
+    return 64;
   } else if constexpr (P == PREC_F32) {
     constexpr int waves = S::NT / 64;
     constexpr bool even16 = (S::BM * 16 * 4 / 1024) % waves == 0 && (S::BN * 16 * 4 / 1024) % waves == 0;
