@@ -200,10 +200,12 @@ template <int BM_, int BN_, int WM_, int WN_, int KS_ = 1, int KB_ = 0, int LDW_
 // K-tile depth of a (precision, shape) pair on the direct-to-LDS path:
 // binary64 tiles of 128 x 128 outputs with 8 waves (one workgroup per CU)
 // take 32-deep K-tiles (twice the MFMA work per barrier), and so does the
-// 4-wave 32 x 32 tile, which runs one workgroup per CU at the small sizes
-// it serves and waits on each K-tile's transfers there (half as many round
-// trips: N = 500 15.6 -> 12.8 us, N = 700 27.3 -> 23.6); the others keep
-// 16 so that two or more workgroups fit in LDS. binary32 takes 16 unless a
+// 4-wave 32 x 32 and 64 x 64 tiles, which run one or two workgroups per CU
+// at the sizes they serve and wait on each K-tile's transfers there (half
+// as many round trips: N = 500 15.6 -> 12.8 us, N = 700 27.3 -> 23.6 on
+// 32 x 32; N = 1400 110.5 -> 98.5, N = 3600 +2% on 64 x 64, N = 1500 and
+// 1700 0.7% and 1.7% slower); the others keep 16 so that two or more
+// workgroups fit in LDS. binary32 takes 16 unless a
 // 16-deep K-tile of A or B is fewer 1 KiB transfers than the shape has
 // waves (the 8-wave 128 x 64 and 64 x 64 shapes), then 32, and 32 on the
 // 4-wave 128 x 128 tile (two workgroups of 64 KiB per CU: 131.8 against
@@ -213,7 +215,7 @@ template <int P, class S> __host__ __device__ constexpr int bk_of() {
   if constexpr (S::KB > 0) {
     return S::KB;
   } else if constexpr (P == PREC_F64) {
-    return (S::BM * S::BN >= 128 * 128 && S::NT >= 512) || (S::BM * S::BN <= 32 * 32 && S::KS == 1)
+    return (S::BM * S::BN >= 128 * 128 && S::NT >= 512) || (S::BM * S::BN <= 64 * 64 && S::KS == 1 && S::NT == 256)
                ? 32 : 16;
   } else if constexpr ((P == PREC_F32 || P == PREC_BF16) && S::BM * S::BN <= 32 * 32 &&
                        S::KS == 1 && S::NT == 256) {
