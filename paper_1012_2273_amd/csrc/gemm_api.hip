@@ -244,6 +244,14 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   // layout has no such kernel
   if (!plain_offered(prec, layout, pick, vw)) pick = fallback_rule(prec, m, n);
   if (!plain_offered(prec, layout, pick, vw)) pick = CFG_128x128_W8;
+  // binary64 mid tier: while the 32 x 32 tiles fit in one round of the
+  // workgroups the CUs hold, they beat the 16-wave 64 x 64 tile (N = 800:
+  // 625 tiles in 768 slots, 30.7 against 37.2 us; N = 900: 841 tiles, a
+  // second round, 49.3 against 41.2)
+  if (prec == PREC_F64 && pick == CFG_64x64_K4 && plain_offered(prec, layout, CFG_32x32, vw)) {
+    const int64_t t32 = ((m + 31) / 32) * ((n + 31) / 32);
+    if (t32 <= device_cus() * (int64_t)occupancy(prec, layout, CFG_32x32, vw)) pick = CFG_32x32;
+  }
   if (prec != PREC_F64 && prec != PREC_F32) return pick;
   const int alt = prec == PREC_F64 ? CFG_64x64 : CFG_64x64_K2;
   if (kCfgs[pick].bm < 128 || shape_rate(prec, pick) <= 0.0) return pick;
