@@ -244,11 +244,14 @@ static int choose_cfg(int prec, int layout, int vw, int64_t m, int64_t n) {
   // layout has no such kernel
   if (!plain_offered(prec, layout, pick, vw)) pick = fallback_rule(prec, m, n);
   if (!plain_offered(prec, layout, pick, vw)) pick = CFG_128x128_W8;
-  // binary64 mid tier: while the 32 x 32 tiles fit in one round of the
-  // workgroups the CUs hold, they beat the 16-wave 64 x 64 tile (N = 800:
-  // 625 tiles in 768 slots, 30.7 against 37.2 us; N = 900: 841 tiles, a
-  // second round, 49.3 against 41.2)
-  if (prec == PREC_F64 && pick == CFG_64x64_K4 && plain_offered(prec, layout, CFG_32x32, vw)) {
+  // Plain products just above the small tier: while the 32 x 32 tiles fit
+  // in one round of the workgroups the CUs hold, they beat the mid-tier
+  // shapes (binary64 N = 800: 625 tiles in 768 slots, 31.0 against 35.9 us
+  // on the 16-wave 64 x 64 tile; binary32 21.7 -> 18.6, bf16 11.5 -> 10.1;
+  // N = 896: 784 tiles, a second round, 39.6 against 39.6, binary32 27.5
+  // against 23.8)
+  if ((prec == PREC_F64 || prec == PREC_F32 || prec == PREC_BF16) && pick != CFG_32x32 &&
+      plain_offered(prec, layout, CFG_32x32, vw)) {
     const int64_t t32 = ((m + 31) / 32) * ((n + 31) / 32);
     if (t32 <= device_cus() * (int64_t)occupancy(prec, layout, CFG_32x32, vw)) pick = CFG_32x32;
   }
